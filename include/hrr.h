@@ -1,0 +1,296 @@
+/*
+ * hrr.h -- C ABI of the MI355X (gfx950) hierarchical Russian-roulette library.
+ *
+ * The library culls the product set of eye vertices {e_j} x light vertices
+ * {l_i} by hierarchical Russian roulette with a deterministic, per-eye rotated
+ * base-2 radical inverse, following J. Pantaleoni, "Blue-Noise Dithered QMC
+ * Hierarchical Russian Roulette":
+ *
+ *   - lights are sorted by a spatial hierarchy and the sort position is the
+ *     sequence index i; every hierarchy node covers a contiguous index range
+ *     [a_n, b_n) (Section 1);
+ *   - eye j draws xi_ij = (Phi_2(i) + r_j) mod 1, Phi_2 the base-2 radical
+ *     inverse and r_j a Cranley-Patterson rotation from a 64x64 dither tile
+ *     (Section 1, equation for phi_j, and the teaser figure);
+ *   - the traversal computes, at every node, v(a_n, b_n) = min over the range
+ *     of xi (Section 1, equation for v(a,b); Section 2 and Algorithms 2-3 give
+ *     the range-minimum method) and culls the subtree when that minimum
+ *     cannot pass the node's acceptance bound;
+ *   - an extra rotation psi(n) can be folded into the shift to draw several
+ *     samples per pair (Section 3).
+ *
+ * Fixed point.  All values in [0,1) are 32-bit fixed point: x is stored as
+ * floor(x * 2^32).  Phi_2(i) is bit_reverse32(i); the rotated value is
+ * xi_ij = (bit_reverse32(i) + r_j) mod 2^32, exact.
+ *
+ * Acceptance.  For pair (j, i) the probability is p = min(1, s / d^2),
+ * d^2 = (dx*dx + dy*dy) + dz*dz with d = l_i - e_j, all in IEEE binary32 with
+ * each operation rounded (no fused multiply-add) and a correctly rounded
+ * division.  The pair is kept when xi_ij / 2^32 < p, i.e. when
+ * xi_ij < ceil(p * 2^32).  Culling never changes this set: a node is dropped
+ * only when its range minimum already fails a bound that is at least the
+ * probability of every light inside the node's box.
+ *
+ * Memory.  Pointers documented as "device" must point to device memory of the
+ * context's GPU (for example torch tensors' data_ptr()); "host" pointers are
+ * ordinary process memory.  The caller owns every buffer it passes in;
+ * hierarchies and server results are owned by the context until freed or
+ * released.  Streams are hipStream_t passed as void* (NULL = default stream).
+ *
+ * Errors.  Every call returns an hrr_status; nothing throws across the ABI.
+ * hrr_last_error() returns a message for the last failing call on that
+ * context (thread-local to the calling thread).
+ *
+ * Threads.  hrr_submit / hrr_poll / hrr_wait / hrr_cancel / hrr_release and
+ * the server statistics call are thread-safe.  All other calls on one context
+ * must not run concurrently.
+ */
+#ifndef HRR_H
+#define HRR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum hrr_status {
+    HRR_OK = 0,
+    HRR_E_INVALID = 1,   /* bad argument: null pointer, size, empty range, non-finite input */
+    HRR_E_NOMEM = 2,     /* device memory or the server budget cannot hold the request */
+    HRR_E_OVERFLOW = 3,  /* output capacity too small; the true count is still reported */
+    HRR_E_DEVICE = 4,    /* a HIP runtime call failed, or a kernel reported an internal error */
+    HRR_E_NOTREADY = 5,  /* served request not finished yet */
+    HRR_E_CANCELLED = 6, /* served request was cancelled */
+    HRR_E_BUSY = 7       /* server not running, or queue full */
+} hrr_status;
+
+typedef struct hrr_ctx hrr_ctx;
+typedef struct hrr_hierarchy hrr_hierarchy;
+
+/* ------------------------------------------------------------------------- */
+/* Context                                                                    */
+/* ------------------------------------------------------------------------- */
+
+/* Create a context on HIP device `device` with the 64x64 dither tile `tile`
+ * (host, 4096 u32, row-major: entry (x mod 64) * 64 + (y mod 64) is the shift
+ * of pixel (x, y)).  The tile is copied to the device.  Section 1 of the
+ * paper: shifts come from a tile laid over the image plane. */
+hrr_status hrr_create(int device, const uint32_t* tile, hrr_ctx** out);
+void hrr_destroy(hrr_ctx* ctx);
+const char* hrr_last_error(const hrr_ctx* ctx);
+const char* hrr_status_string(hrr_status s);
+/* Library version as 10000 * major + 100 * minor + patch. */
+int hrr_version(void);
+
+/* ------------------------------------------------------------------------- */
+/* Range minimum of the rotated radical inverse                               */
+/* ------------------------------------------------------------------------- */
+
+#define HRR_RMQ_PAPER 0u   /* the paper's sweep (Section 2, Algorithms 2 and 3) */
+#define HRR_RMQ_DIRECT 1u  /* same case analysis, each sweep resolved in O(1) bit arithmetic (ablation) */
+
+/* For q < n: k = argmin over i in [a[q], b[q]) of (bit_reverse32(i) + r[q])
+ * mod 2^32 and v = that minimum (Section 1, v(a,b); Section 2, the argmin
+ * form k).  The argmin is unique (the map is a bijection).
+ * a, b, r: device u32[n]; argmin_out, min_out: device u32[n].
+ * A query with a[q] >= b[q] is empty: it yields argmin = b[q] and
+ * min = 0xFFFFFFFF (the paper marks an invalid k with b), and is counted in
+ * *n_invalid_dev (device u64, optional, added to atomically).
+ * Asynchronous on `stream`; returns HRR_E_INVALID for null pointers or an
+ * unknown method, HRR_E_DEVICE if the launch fails. */
+hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint32_t* b,
+                         const uint32_t* r, uint64_t n, uint32_t method,
+                         uint32_t* argmin_out, uint32_t* min_out,
+                         unsigned long long* n_invalid_dev, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Light hierarchy                                                            */
+/* ------------------------------------------------------------------------- */
+
+typedef struct hrr_hierarchy_info {
+    uint32_t n_lights;
+    uint32_t leaf_size;
+    uint32_t n_nodes;       /* internal nodes */
+    uint32_t depth;         /* deepest internal node (root = 0) */
+    uint64_t device_bytes;  /* nodes + sorted lights + permutation */
+    float box[6];           /* root bounding box lo xyz, hi xyz */
+} hrr_hierarchy_info;
+
+/* Build a binary light hierarchy (Section 1: lights sorted by a hierarchy,
+ * each node a contiguous range of sequence indices).  lights_xyz: host,
+ * 3*n_lights fp32.  Lights are ordered by ascending (Morton code, original
+ * index); the Morton code interleaves 21-bit cell indices of x, y, z
+ * (x highest) against `box` (host, 6 floats lo xyz hi xyz; NULL = unit cube;
+ * coordinates outside are clamped for ordering only).  A node [a,b) with
+ * b - a > leaf_size is split at the first index whose code has the highest
+ * bit in which code[a] and code[b-1] differ (midpoint if they are equal).
+ * leaf_size in [1, 8].  Non-finite coordinates return HRR_E_INVALID.
+ * The hierarchy lives on the context's device until hrr_free_hierarchy. */
+hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz,
+                               uint32_t n_lights, uint32_t leaf_size,
+                               const float* box, hrr_hierarchy** out);
+hrr_status hrr_hierarchy_get_info(const hrr_hierarchy* h, hrr_hierarchy_info* out);
+/* perm_out (host u32[n_lights]): perm_out[i] = original index of the light
+ * with sequence index i. */
+hrr_status hrr_hierarchy_permutation(const hrr_hierarchy* h, uint32_t* perm_out);
+/* sorted_xyz_out (host fp32[3*n_lights]): light positions in sequence order. */
+hrr_status hrr_hierarchy_sorted_lights(const hrr_hierarchy* h, float* sorted_xyz_out);
+void hrr_free_hierarchy(hrr_ctx* ctx, hrr_hierarchy* h);
+
+/* ------------------------------------------------------------------------- */
+/* Traversal                                                                  */
+/* ------------------------------------------------------------------------- */
+
+/* An eye set (device memory).  Eye j (0 <= j < n) has position
+ * xyz[3j..3j+2] and pixel p = pixel_base + j at (p mod width, p div width);
+ * its shift is r_j = tile[(x mod 64) * 64 + (y mod 64)] + shift_offset
+ * (mod 2^32).  shift_offset is an extra rotation absorbed into the shift
+ * (Section 3). */
+typedef struct hrr_eyes {
+    const float* xyz;
+    uint32_t n;
+    uint32_t width;
+    uint32_t shift_offset;
+    uint32_t pixel_base;
+} hrr_eyes;
+
+#define HRR_F_STATS 1u      /* count node visits, range minima, leaf tests (slower) */
+
+typedef struct hrr_traverse_opts {
+    uint32_t eyes_per_wave; /* 0 = autotuned; else 1, 2, 4 or 8 eyes share one wavefront */
+    uint32_t stack_entries; /* 0 = autotuned; else LDS stack entries per wave, power of two in [256, 4096] */
+    uint32_t rmq_method;    /* HRR_RMQ_PAPER (default) or HRR_RMQ_DIRECT */
+    uint32_t n_samples;     /* 0 or 1 = one sample per pair; > 1: Section 3 multi-sample */
+    uint32_t psi_s0;        /* start of the golden-ratio lattice psi(n) = s0 + n * alpha mod 1 */
+    uint32_t flags;         /* HRR_F_* */
+} hrr_traverse_opts;
+
+typedef struct hrr_stats {
+    uint64_t eyes;          /* (virtual) eyes traversed */
+    uint64_t pairs;         /* accepted pairs (true count, also past capacity) */
+    uint64_t node_visits;   /* internal nodes popped (each tests both children) */
+    uint64_t rmq_calls;     /* range minima computed with the paper's method */
+    uint64_t leaf_tests;    /* exact per-light acceptance tests */
+    uint64_t spills;        /* stack chunks moved between LDS and device memory */
+    uint64_t max_stack;     /* deepest stack seen by any wave */
+} hrr_stats;
+
+/* Hierarchical Russian roulette of every eye of `eyes` against `h`.
+ *
+ * Output: the accepted pairs as u32 (j, i) in pairs_out (device,
+ * 2*capacity u32), i the sequence index (see hrr_hierarchy_permutation), in
+ * unspecified order.  With n_samples = N > 1 the first component is
+ * j * N + n for sample n, and sample n uses r_j + psi(n).
+ * weights_out (device fp32[capacity], optional): 1/p for each emitted pair,
+ * the Russian-roulette weight (IEEE binary32 reciprocal of p).
+ * *n_pairs (host) receives the true number of accepted pairs; if it exceeds
+ * `capacity` only the first `capacity` are stored and HRR_E_OVERFLOW is
+ * returned (resize and call again).  stats (host, optional) is filled when
+ * opts->flags has HRR_F_STATS.  s must be finite and > 0.
+ * Synchronous: returns after the kernel has finished on `stream`. */
+hrr_status hrr_traverse(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes* eyes,
+                        float s, const hrr_traverse_opts* opts, uint32_t* pairs_out,
+                        float* weights_out, uint64_t capacity, uint64_t* n_pairs,
+                        hrr_stats* stats, void* stream);
+
+/* One unit of a batched launch: an eye set against one hierarchy, with its
+ * own slice [out_offset, out_offset + out_capacity) of the output buffers. */
+typedef struct hrr_work_item {
+    const hrr_hierarchy* h;
+    hrr_eyes eyes;
+    float s;
+    uint32_t reserved;
+    uint64_t out_offset;
+    uint64_t out_capacity;
+} hrr_work_item;
+
+/* Many independent (hierarchy, eye set) items in ONE persistent launch fed by
+ * a device work queue.  items: host array.  counts_out (host u64[n_items])
+ * receives each item's true pair count; items whose count exceeds their
+ * capacity store only the first out_capacity pairs and make the call return
+ * HRR_E_OVERFLOW.  Other arguments as hrr_traverse.  Synchronous. */
+hrr_status hrr_traverse_batched(hrr_ctx* ctx, const hrr_work_item* items,
+                                uint32_t n_items, const hrr_traverse_opts* opts,
+                                uint32_t* pairs_out, float* weights_out,
+                                uint64_t* counts_out, hrr_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------- */
+/* Autotuner                                                                  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct hrr_tune_result {
+    uint32_t eyes_per_wave;
+    uint32_t stack_entries;
+    uint32_t leaf_size;
+    float ms;               /* best measured time of the probe launch */
+} hrr_tune_result;
+
+/* Time candidate launch shapes (eyes per wave x stack entries) for eyes of
+ * `eyes` against each hierarchy in hs[0..n_h) -- normally the same lights
+ * built with different leaf sizes -- and remember the fastest for hierarchies
+ * of this size class and this eye count class.  Later launches with
+ * eyes_per_wave = 0 or stack_entries = 0 use the remembered choice.  The
+ * probe uses at most max_probe_eyes eyes and a scratch output the library
+ * allocates.  best (host, optional) receives the winner. */
+hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs, uint32_t n_h,
+                        const hrr_eyes* eyes, float s, uint32_t max_probe_eyes,
+                        hrr_tune_result* best, void* stream);
+/* The leaf size the tuner prefers for hierarchies of n_lights lights (0 if none tuned). */
+uint32_t hrr_tuned_leaf_size(const hrr_ctx* ctx, uint32_t n_lights);
+
+/* ------------------------------------------------------------------------- */
+/* Serving: resident hierarchies, continuous batching of eye tiles            */
+/* ------------------------------------------------------------------------- */
+
+typedef struct hrr_server_config {
+    uint64_t hbm_budget_bytes;   /* device memory for request eyes + results */
+    uint32_t max_inflight;       /* launches in flight at once (one stream each), 1..8 */
+    uint32_t max_batch_eyes;     /* eyes per launch before a batch is closed */
+    uint32_t max_batch_items;    /* requests per launch */
+    uint32_t eyes_per_wave;      /* 0 = autotuned */
+    float pairs_per_eye_guess;   /* initial output reservation per eye (adapted online) */
+} hrr_server_config;
+
+typedef struct hrr_server_stats {
+    uint64_t submitted, completed, cancelled, rejected, launches, retries;
+    uint64_t pairs;
+    double p50_ms, p99_ms, mean_ms; /* submit -> complete latency of completed requests */
+    double busy_s;                  /* wall time with at least one launch in flight */
+    uint64_t peak_bytes;            /* high-water mark of the budget in use */
+} hrr_server_stats;
+
+typedef struct hrr_ticket_info {
+    double submit_s, start_s, done_s;  /* host monotonic clock, seconds */
+    uint64_t n_pairs;
+    uint32_t launches;                 /* > 1 if the request was re-run after an output overflow */
+} hrr_ticket_info;
+
+/* Start the serving loop (host threads).  The budget is allocated once. */
+hrr_status hrr_server_start(hrr_ctx* ctx, const hrr_server_config* cfg);
+/* Stop: waits for in-flight launches, cancels queued requests. */
+hrr_status hrr_server_stop(hrr_ctx* ctx);
+/* Queue a request: an eye tile (host xyz, 3*n_eyes fp32, copied) against a
+ * resident hierarchy, with its own shift offset and s.  Returns a ticket.
+ * HRR_E_NOMEM if the tile could never fit the budget, HRR_E_BUSY if the
+ * server is not running. */
+hrr_status hrr_submit(hrr_ctx* ctx, const hrr_hierarchy* h, const float* eyes_xyz,
+                      uint32_t n_eyes, uint32_t width, uint32_t shift_offset,
+                      float s, uint64_t* ticket);
+/* HRR_E_NOTREADY until the request is complete; then HRR_OK with the device
+ * address of its (j, i) pairs (valid until hrr_release) and the count. */
+hrr_status hrr_poll(hrr_ctx* ctx, uint64_t ticket, const uint32_t** pairs_dev,
+                    uint64_t* n_pairs, hrr_ticket_info* info);
+/* Block until complete or timeout_ms elapses (HRR_E_NOTREADY). */
+hrr_status hrr_wait(hrr_ctx* ctx, uint64_t ticket, uint32_t timeout_ms);
+/* Cancel a request that has not started; HRR_E_BUSY if it already runs. */
+hrr_status hrr_cancel(hrr_ctx* ctx, uint64_t ticket);
+/* Free a completed or cancelled request's result memory. */
+hrr_status hrr_release(hrr_ctx* ctx, uint64_t ticket);
+hrr_status hrr_server_get_stats(hrr_ctx* ctx, hrr_server_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HRR_H */

@@ -81,6 +81,8 @@ def lib():
     L.or_accept_prob.argtypes = [P, P, ctypes.c_float]
     L.or_accept.restype = i32
     L.or_accept.argtypes = [P, P, ctypes.c_float, u32]
+    L.or_accept_weight.restype = ctypes.c_float
+    L.or_accept_weight.argtypes = [P, P, ctypes.c_float]
     L.or_fingerprint_hash.restype = u64
     L.or_fingerprint_hash.argtypes = [u64]
     L.or_accept_eyes.restype = None
@@ -184,6 +186,12 @@ def accept_prob(e, l, s: float) -> float:
 def accept(e, l, s: float, xi: int) -> bool:
     e, l = _c(e, np.float32), _c(l, np.float32)
     return bool(lib().or_accept(_ptr(e), _ptr(l), float(s), int(xi)))
+
+
+def accept_weight(e, l, s: float) -> float:
+    """1 / p of the pair in binary32."""
+    e, l = _c(e, np.float32), _c(l, np.float32)
+    return float(lib().or_accept_weight(_ptr(e), _ptr(l), float(s)))
 
 
 def fingerprint_hash(i: int) -> int:

@@ -284,6 +284,13 @@ OR_EXPORT int or_accept(const float* e, const float* l, float s, uint32_t xi) {
     return (double)xi < t;
 }
 
+/* Russian-roulette weight of a kept pair: 1 / p in binary32 (correctly
+ * rounded reciprocal), the factor that keeps the culled estimator unbiased
+ * (Section 1: roulette with probability p). */
+OR_EXPORT float or_accept_weight(const float* e, const float* l, float s) {
+    return 1.0f / or_accept_prob(e, l, s);
+}
+
 /* ------------------------------------------------------------------------- */
 /* All-pairs accepted set for a selection of eyes.                            */
 /* ------------------------------------------------------------------------- */

@@ -1,0 +1,604 @@
+// hrr_api.cpp -- C ABI: context, range minimum, hierarchy, traversal,
+// batched traversal and autotuner.  The serving loop is in hrr_serve.cpp.
+#include <hip/hip_runtime_api.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <vector>
+
+#include "hrr_ctx.hpp"
+
+#define HRR_EXPORT extern "C" __attribute__((visibility("default")))
+
+// kernels (hrr_kernels.hip)
+extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const uint32_t* r, uint64_t n,
+                                     uint32_t method, uint32_t* k, uint32_t* v, unsigned long long* n_bad,
+                                     int n_cu, hipStream_t stream);
+extern "C" hipError_t hrr_launch_traverse(const hrr::TravArgs* A, uint32_t eyes_per_wave, uint32_t method,
+                                          int stats, int with_weights, uint32_t blocks, hipStream_t stream);
+extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap, int with_weights);
+extern "C" size_t hrr_trav_lds_per_block(uint32_t n_items, size_t lds_per_wave);
+extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t method, int stats, int with_weights,
+                                             size_t lds_per_block, int* blocks_per_cu);
+
+namespace hrr {
+
+static thread_local std::string g_err;
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+hrr_status fail(hrr_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+hrr_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? HRR_E_NOMEM : HRR_E_DEVICE;
+}
+
+int ilog2_floor(uint64_t x) { return x ? 63 - __builtin_clzll(x) : 0; }
+
+hipError_t DevBuf::ensure(size_t want) {
+    if (want <= bytes) return hipSuccess;
+    if (p) {
+        hipError_t e = hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t sz = std::max<size_t>(want, 256);
+    hipError_t e = hipMalloc(&p, sz);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    bytes = sz;
+    return hipSuccess;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+void release_scratch(LaunchScratch& S) {
+    S.items.release();
+    S.task_begin.release();
+    S.counters.release();
+    S.misc.release();
+    S.spill.release();
+    if (S.h_pinned) (void)hipHostFree(S.h_pinned);
+    S.h_pinned = nullptr;
+    S.h_pinned_n = 0;
+}
+
+static bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+
+void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes, uint32_t* epw,
+                   uint32_t* cap) {
+    uint32_t e = opts ? opts->eyes_per_wave : 0;
+    uint32_t c = opts ? opts->stack_entries : 0;
+    if (e == 0 || c == 0) {
+        TuneVal tv{0, 0, 0, 0.f};
+        bool found = false;
+        {
+            std::lock_guard<std::mutex> g(ctx->tune_mu);
+            const TuneKey key{ilog2_floor(n_lights), ilog2_floor(n_eyes)};
+            auto it = ctx->tune.find(key);
+            if (it == ctx->tune.end()) {
+                // nearest tuned light class for this eye class, else any
+                int best = 1 << 30;
+                for (auto& kv : ctx->tune) {
+                    const int d = abs(kv.first.log_lights - key.log_lights) * 4 + abs(kv.first.log_eyes - key.log_eyes);
+                    if (d < best) {
+                        best = d;
+                        tv = kv.second;
+                        found = true;
+                    }
+                }
+            } else {
+                tv = it->second;
+                found = true;
+            }
+        }
+        if (e == 0) e = found ? tv.eyes_per_wave : (n_lights >= (1u << 14) ? 1u : n_lights >= (1u << 11) ? 2u : 4u);
+        if (c == 0) c = found ? tv.stack_entries : 512u;
+    }
+    *epw = e;
+    *cap = c;
+}
+
+hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
+                        uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
+                        uint32_t* pairs, float* weights, hipStream_t stream) {
+    const size_t n = items.size();
+    if (n == 0 || n > kMaxItemsPerLaunch) return fail(HRR_E_INVALID, "items per launch must be in [1, %u]", kMaxItemsPerLaunch);
+    if (!(epw == 1 || epw == 2 || epw == 4 || epw == 8)) return fail(HRR_E_INVALID, "eyes_per_wave must be 1, 2, 4 or 8");
+    if (!is_pow2(cap) || cap < 256 || cap > 4096) return fail(HRR_E_INVALID, "stack_entries must be a power of two in [256, 4096]");
+    if (method > 1) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
+    if (n_samples == 0) n_samples = 1;
+
+    S.h_items.assign(n, ItemDesc{});
+    S.h_task_begin.assign(n + 1, 0);
+    uint64_t tasks = 0;
+    uint32_t dmax = 0;
+
+    hipError_t e;
+    if ((e = S.counters.ensure(n * sizeof(unsigned long long))) != hipSuccess) return hip_fail(e, "counters");
+    if ((e = S.misc.ensure(16 * sizeof(unsigned long long))) != hipSuccess) return hip_fail(e, "misc");
+    unsigned long long* d_counters = static_cast<unsigned long long*>(S.counters.p);
+    unsigned long long* d_misc = static_cast<unsigned long long*>(S.misc.p);
+
+    for (size_t k = 0; k < n; ++k) {
+        const HostItem& it = items[k];
+        const hrr_hierarchy* h = it.h;
+        if (!h) return fail(HRR_E_INVALID, "item %zu: null hierarchy", k);
+        if (h->owner != ctx) return fail(HRR_E_INVALID, "item %zu: hierarchy belongs to another context", k);
+        if (!(it.s > 0.0f) || !isfinite(it.s)) return fail(HRR_E_INVALID, "item %zu: s must be finite and > 0", k);
+        if (it.eyes.n > 0 && !it.eyes.xyz) return fail(HRR_E_INVALID, "item %zu: null eye positions", k);
+        if (it.eyes.width == 0) return fail(HRR_E_INVALID, "item %zu: width must be >= 1", k);
+        if (it.out_capacity > 0 && !pairs) return fail(HRR_E_INVALID, "item %zu: null pairs buffer", k);
+        const uint64_t nv = (uint64_t)it.eyes.n * n_samples;
+        if (nv > 0xFFFFFFFFull) return fail(HRR_E_INVALID, "item %zu: eyes x samples exceeds 2^32 - 1", k);
+        ItemDesc& D = S.h_items[k];
+        D.nodes = h->d_nodes;
+        D.lights = h->d_lights;
+        D.eyes = it.eyes.xyz;
+        D.pairs = pairs ? pairs + 2 * it.out_offset : nullptr;
+        D.weights = weights ? weights + it.out_offset : nullptr;
+        D.counter = d_counters + k;
+        D.capacity = it.out_capacity;
+        D.n_lights = h->n_lights;
+        D.n_nodes = h->n_nodes;
+        D.leaf_size = h->leaf_size;
+        D.n_virtual = h->n_lights ? (uint32_t)nv : 0u;   // no lights: nothing to do
+        D.width = it.eyes.width;
+        D.shift_offset = it.eyes.shift_offset;
+        D.pixel_base = it.eyes.pixel_base;
+        D.n_samples = n_samples;
+        D.psi_s0 = psi_s0;
+        D.s = it.s;
+        for (int q = 0; q < 3; ++q) {
+            D.root_lo[q] = h->box[q];
+            D.root_hi[q] = h->box[3 + q];
+        }
+        D.task_begin = (uint32_t)tasks;
+        S.h_task_begin[k] = (uint32_t)tasks;
+        tasks += (D.n_virtual + epw - 1) / epw;
+        if (tasks > 0xFFFFFFF0ull) return fail(HRR_E_INVALID, "too many tasks in one launch");
+        dmax = std::max(dmax, h->depth);
+    }
+    S.h_task_begin[n] = (uint32_t)tasks;
+
+    // pinned staging: items, task table, then readback words
+    const size_t items_bytes = n * sizeof(ItemDesc);
+    const size_t tb_bytes = (n + 1) * sizeof(uint32_t);
+    const size_t read_words = n + 1 + ST_N;
+    const size_t pin_words = read_words + (items_bytes + tb_bytes + 7) / 8 + 2;
+    if (S.h_pinned_n < pin_words) {
+        if (S.h_pinned) (void)hipHostFree(S.h_pinned);
+        S.h_pinned = nullptr;
+        S.h_pinned_n = 0;
+        if ((e = hipHostMalloc((void**)&S.h_pinned, pin_words * 8, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "pinned staging");
+        S.h_pinned_n = pin_words;
+    }
+    unsigned char* up = reinterpret_cast<unsigned char*>(S.h_pinned + read_words);
+    memcpy(up, S.h_items.data(), items_bytes);
+    memcpy(up + items_bytes, S.h_task_begin.data(), tb_bytes);
+
+    if ((e = S.items.ensure(items_bytes)) != hipSuccess) return hip_fail(e, "item table");
+    if ((e = S.task_begin.ensure(tb_bytes)) != hipSuccess) return hip_fail(e, "task table");
+    if ((e = hipMemcpyAsync(S.items.p, up, items_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "upload items");
+    if ((e = hipMemcpyAsync(S.task_begin.p, up + items_bytes, tb_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "upload tasks");
+    if ((e = hipMemsetAsync(d_counters, 0, n * sizeof(unsigned long long), stream)) != hipSuccess)
+        return hip_fail(e, "clear counters");
+    if ((e = hipMemsetAsync(d_misc, 0, 16 * sizeof(unsigned long long), stream)) != hipSuccess)
+        return hip_fail(e, "clear misc");
+
+    if (tasks > 0) {
+        const int with_w = weights != nullptr;
+        const size_t lds_wave = hrr_trav_lds_per_wave(cap, with_w);
+        const size_t lds_block = hrr_trav_lds_per_block((uint32_t)n, lds_wave);
+        int bpc = 0;
+        if ((e = hrr_traverse_occupancy(epw, method, stats, with_w, lds_block, &bpc)) != hipSuccess)
+            return hip_fail(e, "occupancy");
+        if (bpc <= 0) return fail(HRR_E_INVALID, "stack of %u entries does not fit in LDS", cap);
+        const uint64_t need_blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+        const uint32_t blocks = (uint32_t)std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, need_blocks);
+        const uint32_t half = cap / 2;
+        const uint64_t bound = 128ull * (dmax + 2);
+        const uint32_t spill_cap = (uint32_t)(((bound + half - 1) / half) * half + half);
+        const size_t spill_bytes = (size_t)blocks * kWavesPerBlock * spill_cap * sizeof(unsigned long long);
+        if ((e = S.spill.ensure(spill_bytes)) != hipSuccess) return hip_fail(e, "spill stacks");
+
+        TravArgs A;
+        memset(&A, 0, sizeof A);
+        A.items = static_cast<const ItemDesc*>(S.items.p);
+        A.task_begin = static_cast<const uint32_t*>(S.task_begin.p);
+        A.n_items = (uint32_t)n;
+        A.n_tasks = (uint32_t)tasks;
+        A.task_counter = reinterpret_cast<uint32_t*>(d_misc + 0);
+        A.tile = ctx->d_tile;
+        A.spill = static_cast<unsigned long long*>(S.spill.p);
+        A.spill_cap = spill_cap;
+        A.stack_cap = cap;
+        A.lds_per_wave = (uint32_t)lds_wave;
+        A.stats = stats ? d_misc + 2 : nullptr;
+        A.error = reinterpret_cast<uint32_t*>(d_misc + 1);
+        if ((e = hrr_launch_traverse(&A, epw, method, stats, with_w, blocks, stream)) != hipSuccess)
+            return hip_fail(e, "traverse launch");
+    }
+    if ((e = hipMemcpyAsync(S.h_pinned, d_counters, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream)) !=
+        hipSuccess)
+        return hip_fail(e, "read counters");
+    if ((e = hipMemcpyAsync(S.h_pinned + n, d_misc + 1, (1 + ST_N) * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, stream)) != hipSuccess)
+        return hip_fail(e, "read status");
+    return HRR_OK;
+}
+
+static void fill_stats(const unsigned long long* st, hrr_stats* out) {
+    out->eyes = st[ST_EYES];
+    out->pairs = st[ST_PAIRS];
+    out->node_visits = st[ST_VISITS];
+    out->rmq_calls = st[ST_RMQ];
+    out->leaf_tests = st[ST_LEAF];
+    out->spills = st[ST_SPILLS];
+    out->max_stack = st[ST_MAXSTACK];
+}
+
+}  // namespace hrr
+
+using namespace hrr;
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+HRR_EXPORT int hrr_version(void) { return 10000 * 0 + 100 * 1 + 0; }
+
+HRR_EXPORT const char* hrr_status_string(hrr_status s) {
+    switch (s) {
+        case HRR_OK: return "ok";
+        case HRR_E_INVALID: return "invalid argument";
+        case HRR_E_NOMEM: return "out of memory";
+        case HRR_E_OVERFLOW: return "output capacity exceeded";
+        case HRR_E_DEVICE: return "device error";
+        case HRR_E_NOTREADY: return "not ready";
+        case HRR_E_CANCELLED: return "cancelled";
+        case HRR_E_BUSY: return "busy";
+    }
+    return "unknown status";
+}
+
+HRR_EXPORT const char* hrr_last_error(const hrr_ctx*) { return g_err.c_str(); }
+
+HRR_EXPORT hrr_status hrr_create(int device, const uint32_t* tile, hrr_ctx** out) {
+    if (!out || !tile) return fail(HRR_E_INVALID, "hrr_create: null argument");
+    *out = nullptr;
+    int n_dev = 0;
+    hipError_t e = hipGetDeviceCount(&n_dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n_dev) return fail(HRR_E_INVALID, "device %d not present (%d devices)", device, n_dev);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipDeviceProp_t prop;
+    if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    hrr_ctx* c = new hrr_ctx();
+    c->device = device;
+    c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    if ((e = hipMalloc((void**)&c->d_tile, 4096 * sizeof(uint32_t))) != hipSuccess) {
+        delete c;
+        return hip_fail(e, "tile");
+    }
+    if ((e = hipMemcpy(c->d_tile, tile, 4096 * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(c->d_tile);
+        delete c;
+        return hip_fail(e, "tile upload");
+    }
+    *out = c;
+    return HRR_OK;
+}
+
+extern void hrr_server_shutdown(hrr_ctx* ctx);   // hrr_serve.cpp
+
+HRR_EXPORT void hrr_destroy(hrr_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    hrr_server_shutdown(ctx);
+    release_scratch(ctx->scratch);
+    if (ctx->d_tile) (void)hipFree(ctx->d_tile);
+    delete ctx;
+}
+
+// ---------------------------------------------------------------------------
+// range minimum
+// ---------------------------------------------------------------------------
+
+HRR_EXPORT hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint32_t* b, const uint32_t* r, uint64_t n,
+                                    uint32_t method, uint32_t* argmin_out, uint32_t* min_out,
+                                    unsigned long long* n_invalid_dev, void* stream) {
+    if (!ctx) return fail(HRR_E_INVALID, "hrr_range_min: null context");
+    if (method > 1) return fail(HRR_E_INVALID, "hrr_range_min: unknown method %u", method);
+    if (n == 0) return HRR_OK;
+    if (!a || !b || !r || !argmin_out || !min_out) return fail(HRR_E_INVALID, "hrr_range_min: null array");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    e = hrr_launch_rmq(a, b, r, n, method, argmin_out, min_out, n_invalid_dev, ctx->n_cu, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "range-min launch");
+    return HRR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// hierarchy
+// ---------------------------------------------------------------------------
+
+HRR_EXPORT hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz, uint32_t n_lights, uint32_t leaf_size,
+                                          const float* box, hrr_hierarchy** out) {
+    if (!ctx || !out) return fail(HRR_E_INVALID, "hrr_build_hierarchy: null argument");
+    *out = nullptr;
+    if (n_lights > 0 && !lights_xyz) return fail(HRR_E_INVALID, "hrr_build_hierarchy: null lights");
+    if (leaf_size < 1 || leaf_size > 8) return fail(HRR_E_INVALID, "leaf_size must be in [1, 8]");
+    if (n_lights >= kMaxNodes) return fail(HRR_E_INVALID, "at most %u lights", kMaxNodes - 1);
+    if (box) {
+        for (int k = 0; k < 3; ++k)
+            if (!isfinite(box[k]) || !isfinite(box[3 + k]) || !(box[3 + k] > box[k]))
+                return fail(HRR_E_INVALID, "box must be finite with hi > lo");
+    }
+    HostHierarchy H;
+    if (!build_hierarchy(lights_xyz, n_lights, leaf_size, box, H))
+        return fail(HRR_E_INVALID, "non-finite light coordinate");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hrr_hierarchy* h = new hrr_hierarchy();
+    h->owner = ctx;
+    h->n_lights = n_lights;
+    h->leaf_size = leaf_size;
+    h->n_nodes = (uint32_t)H.nodes.size();
+    h->depth = H.depth;
+    memcpy(h->box, H.box, sizeof h->box);
+    const size_t nb = std::max<size_t>(H.nodes.size(), 1) * sizeof(Node);
+    const size_t lb = std::max<size_t>(n_lights, 1) * 4 * sizeof(float);
+    const size_t pb = std::max<size_t>(n_lights, 1) * sizeof(uint32_t);
+    std::vector<float> l4(4 * (size_t)n_lights, 0.0f);
+    for (size_t i = 0; i < n_lights; ++i)
+        for (int k = 0; k < 3; ++k) l4[4 * i + k] = H.sorted_xyz[3 * i + k];
+    if ((e = hipMalloc((void**)&h->d_nodes, nb)) != hipSuccess || (e = hipMalloc((void**)&h->d_lights, lb)) != hipSuccess ||
+        (e = hipMalloc((void**)&h->d_perm, pb)) != hipSuccess) {
+        hrr_free_hierarchy(ctx, h);
+        return hip_fail(e, "hierarchy allocation");
+    }
+    if ((H.nodes.size() && (e = hipMemcpy(h->d_nodes, H.nodes.data(), H.nodes.size() * sizeof(Node), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (n_lights && (e = hipMemcpy(h->d_lights, l4.data(), l4.size() * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (n_lights && (e = hipMemcpy(h->d_perm, H.perm.data(), H.perm.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)) {
+        hrr_free_hierarchy(ctx, h);
+        return hip_fail(e, "hierarchy upload");
+    }
+    h->device_bytes = nb + lb + pb;
+    h->perm = std::move(H.perm);
+    h->sorted_xyz = std::move(H.sorted_xyz);
+    *out = h;
+    return HRR_OK;
+}
+
+HRR_EXPORT hrr_status hrr_hierarchy_get_info(const hrr_hierarchy* h, hrr_hierarchy_info* out) {
+    if (!h || !out) return fail(HRR_E_INVALID, "hrr_hierarchy_get_info: null argument");
+    out->n_lights = h->n_lights;
+    out->leaf_size = h->leaf_size;
+    out->n_nodes = h->n_nodes;
+    out->depth = h->depth;
+    out->device_bytes = h->device_bytes;
+    memcpy(out->box, h->box, sizeof out->box);
+    return HRR_OK;
+}
+
+HRR_EXPORT hrr_status hrr_hierarchy_permutation(const hrr_hierarchy* h, uint32_t* perm_out) {
+    if (!h || (!perm_out && h->n_lights)) return fail(HRR_E_INVALID, "hrr_hierarchy_permutation: null argument");
+    if (h->n_lights) memcpy(perm_out, h->perm.data(), h->n_lights * sizeof(uint32_t));
+    return HRR_OK;
+}
+
+HRR_EXPORT hrr_status hrr_hierarchy_sorted_lights(const hrr_hierarchy* h, float* sorted_xyz_out) {
+    if (!h || (!sorted_xyz_out && h->n_lights)) return fail(HRR_E_INVALID, "hrr_hierarchy_sorted_lights: null argument");
+    if (h->n_lights) memcpy(sorted_xyz_out, h->sorted_xyz.data(), 3 * (size_t)h->n_lights * sizeof(float));
+    return HRR_OK;
+}
+
+HRR_EXPORT void hrr_free_hierarchy(hrr_ctx* ctx, hrr_hierarchy* h) {
+    if (!h) return;
+    if (ctx) (void)hipSetDevice(ctx->device);
+    if (h->d_nodes) (void)hipFree(h->d_nodes);
+    if (h->d_lights) (void)hipFree(h->d_lights);
+    if (h->d_perm) (void)hipFree(h->d_perm);
+    delete h;
+}
+
+// ---------------------------------------------------------------------------
+// traversal
+// ---------------------------------------------------------------------------
+
+static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, const hrr_traverse_opts* opts,
+                           uint32_t* pairs, float* weights, uint64_t* counts, hrr_stats* stats, hipStream_t stream,
+                           uint32_t epw_override = 0, uint32_t cap_override = 0) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    uint64_t max_eyes = 0;
+    uint32_t max_lights = 0;
+    for (auto& it : items) {
+        max_eyes = std::max<uint64_t>(max_eyes, it.eyes.n);
+        if (it.h) max_lights = std::max(max_lights, it.h->n_lights);
+    }
+    uint32_t epw, cap;
+    resolve_shape(ctx, opts, max_lights, max_eyes, &epw, &cap);
+    if (epw_override) epw = epw_override;
+    if (cap_override) cap = cap_override;
+    const uint32_t method = opts ? opts->rmq_method : HRR_RMQ_PAPER;
+    const uint32_t ns = opts && opts->n_samples > 1 ? opts->n_samples : 1;
+    const uint32_t s0 = opts ? opts->psi_s0 : 0;
+    const bool want_stats = opts && (opts->flags & HRR_F_STATS);
+    LaunchScratch& S = ctx->scratch;
+    hrr_status st = launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, pairs, weights, stream);
+    if (st != HRR_OK) return st;
+    if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "traverse");
+    const size_t n = items.size();
+    bool overflow = false;
+    uint64_t total = 0;
+    for (size_t k = 0; k < n; ++k) {
+        counts[k] = S.h_pinned[k];
+        total += counts[k];
+        if (counts[k] > items[k].out_capacity) overflow = true;
+    }
+    const uint32_t err = (uint32_t)S.h_pinned[pinned_error_index(n)];
+    if (stats) {
+        memset(stats, 0, sizeof *stats);
+        if (want_stats) fill_stats(S.h_pinned + pinned_stats_index(n), stats);
+        stats->pairs = total;
+    }
+    if (err) return fail(HRR_E_DEVICE, "traversal kernel reported error %u (stack spill region exhausted)", err);
+    if (overflow) return fail(HRR_E_OVERFLOW, "output capacity exceeded");
+    return HRR_OK;
+}
+
+HRR_EXPORT hrr_status hrr_traverse(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes* eyes, float s,
+                                   const hrr_traverse_opts* opts, uint32_t* pairs_out, float* weights_out,
+                                   uint64_t capacity, uint64_t* n_pairs, hrr_stats* stats, void* stream) {
+    if (!ctx || !h || !eyes || !n_pairs) return fail(HRR_E_INVALID, "hrr_traverse: null argument");
+    *n_pairs = 0;
+    std::vector<HostItem> items{HostItem{h, *eyes, s, 0, capacity}};
+    uint64_t count = 0;
+    hrr_status st = run_sync(ctx, items, opts, pairs_out, weights_out, &count, stats, (hipStream_t)stream);
+    if (st == HRR_OK || st == HRR_E_OVERFLOW) *n_pairs = count;
+    return st;
+}
+
+HRR_EXPORT hrr_status hrr_traverse_batched(hrr_ctx* ctx, const hrr_work_item* items, uint32_t n_items,
+                                           const hrr_traverse_opts* opts, uint32_t* pairs_out, float* weights_out,
+                                           uint64_t* counts_out, hrr_stats* stats, void* stream) {
+    if (!ctx || !items || !counts_out) return fail(HRR_E_INVALID, "hrr_traverse_batched: null argument");
+    if (n_items == 0) return HRR_OK;
+    std::vector<HostItem> v;
+    v.reserve(n_items);
+    for (uint32_t k = 0; k < n_items; ++k)
+        v.push_back(HostItem{items[k].h, items[k].eyes, items[k].s, items[k].out_offset, items[k].out_capacity});
+    return run_sync(ctx, v, opts, pairs_out, weights_out, counts_out, stats, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+
+HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs, uint32_t n_h, const hrr_eyes* eyes,
+                                   float s, uint32_t max_probe_eyes, hrr_tune_result* best, void* stream) {
+    if (!ctx || !hs || n_h == 0 || !eyes) return fail(HRR_E_INVALID, "hrr_autotune: null argument");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    hrr_eyes probe = *eyes;
+    if (max_probe_eyes && probe.n > max_probe_eyes) probe.n = max_probe_eyes;
+    static const uint32_t epws[] = {1, 2, 4, 8};
+    static const uint32_t caps[] = {256, 512, 1024};
+    TuneVal bestv{0, 0, 0, 1e30f};
+    DevBuf out;
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "event");
+    }
+    hrr_status result = HRR_OK;
+    uint32_t n_lights_ref = hs[0]->n_lights;
+    for (uint32_t q = 0; q < n_h && result == HRR_OK; ++q) {
+        const hrr_hierarchy* h = hs[q];
+        if (!h || h->owner != ctx) {
+            result = fail(HRR_E_INVALID, "hrr_autotune: bad hierarchy %u", q);
+            break;
+        }
+        // count pass, then size the scratch output
+        uint64_t cnt = 0;
+        std::vector<HostItem> items{HostItem{h, probe, s, 0, 0}};
+        hrr_status r = run_sync(ctx, items, nullptr, nullptr, nullptr, &cnt, nullptr, st, 1, 512);
+        if (r != HRR_OK && r != HRR_E_OVERFLOW) {
+            result = r;
+            break;
+        }
+        if ((e = out.ensure(std::max<uint64_t>(cnt, 1) * 8)) != hipSuccess) {
+            result = hip_fail(e, "tuner output");
+            break;
+        }
+        items[0].out_capacity = cnt;
+        for (uint32_t epw : epws)
+            for (uint32_t cap : caps) {
+                float ms_best = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    uint64_t c2 = 0;
+                    (void)hipEventRecord(e0, st);
+                    r = run_sync(ctx, items, nullptr, static_cast<uint32_t*>(out.p), nullptr, &c2, nullptr, st, epw, cap);
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    if (r != HRR_OK) break;
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ms_best = std::min(ms_best, ms);
+                }
+                if (r != HRR_OK) {
+                    result = r;
+                    break;
+                }
+                if (ms_best < bestv.ms) bestv = TuneVal{epw, cap, h->leaf_size, ms_best};
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    out.release();
+    if (result != HRR_OK) return result;
+    {
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        ctx->tune[TuneKey{ilog2_floor(n_lights_ref), ilog2_floor(eyes->n)}] = bestv;
+        ctx->tune_leaf[ilog2_floor(n_lights_ref)] = bestv.leaf_size;
+    }
+    if (best) {
+        best->eyes_per_wave = bestv.eyes_per_wave;
+        best->stack_entries = bestv.stack_entries;
+        best->leaf_size = bestv.leaf_size;
+        best->ms = bestv.ms;
+    }
+    return HRR_OK;
+}
+
+HRR_EXPORT uint32_t hrr_tuned_leaf_size(const hrr_ctx* ctx, uint32_t n_lights) {
+    if (!ctx) return 0;
+    hrr_ctx* c = const_cast<hrr_ctx*>(ctx);
+    std::lock_guard<std::mutex> g(c->tune_mu);
+    const int key = ilog2_floor(n_lights);
+    auto it = c->tune_leaf.find(key);
+    if (it != c->tune_leaf.end()) return it->second;
+    int best = 1 << 30;
+    uint32_t v = 0;
+    for (auto& kv : c->tune_leaf)
+        if (abs(kv.first - key) < best) {
+            best = abs(kv.first - key);
+            v = kv.second;
+        }
+    return v;
+}

@@ -1,0 +1,111 @@
+// hrr_ctx.hpp -- private state behind the C ABI (host side only).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hrr.h"
+#include "hrr_build.hpp"
+#include "hrr_types.hpp"
+
+struct hrr_hierarchy {
+    hrr_ctx* owner = nullptr;
+    uint32_t n_lights = 0, leaf_size = 1, n_nodes = 0, depth = 0;
+    float box[6] = {0, 0, 0, 0, 0, 0};
+    hrr::Node* d_nodes = nullptr;
+    float* d_lights = nullptr;       // float4 per light
+    uint32_t* d_perm = nullptr;
+    std::vector<uint32_t> perm;      // host copy
+    std::vector<float> sorted_xyz;   // host copy
+    uint64_t device_bytes = 0;
+};
+
+namespace hrr {
+
+// Device buffer that only grows.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want);
+    void release();
+};
+
+struct TuneKey {
+    int log_lights, log_eyes;
+    bool operator<(const TuneKey& o) const {
+        return log_lights != o.log_lights ? log_lights < o.log_lights : log_eyes < o.log_eyes;
+    }
+};
+
+struct TuneVal {
+    uint32_t eyes_per_wave, stack_entries, leaf_size;
+    float ms;
+};
+
+// Host description of one traversal item before it becomes an ItemDesc.
+struct HostItem {
+    const hrr_hierarchy* h;
+    hrr_eyes eyes;
+    float s;
+    uint64_t out_offset, out_capacity;
+};
+
+// Per-launch device scratch: one set per stream slot so that concurrent
+// launches (the server) never share queue heads or counters.
+struct LaunchScratch {
+    DevBuf items, task_begin, counters, misc, spill;
+    std::vector<ItemDesc> h_items;
+    std::vector<uint32_t> h_task_begin;
+    unsigned long long* h_pinned = nullptr;   // pinned readback area
+    size_t h_pinned_n = 0;
+};
+
+struct Server;
+
+}  // namespace hrr
+
+struct hrr_ctx {
+    int device = 0;
+    int n_cu = 256;
+    uint32_t* d_tile = nullptr;
+    hrr::LaunchScratch scratch;   // scratch of the synchronous entry points
+    std::mutex tune_mu;
+    std::map<hrr::TuneKey, hrr::TuneVal> tune;
+    std::map<int, uint32_t> tune_leaf;   // log2 lights -> leaf size
+    hrr::Server* server = nullptr;
+    std::mutex server_mu;
+};
+
+namespace hrr {
+
+void set_error(const char* fmt, ...);
+hrr_status fail(hrr_status st, const char* fmt, ...);
+hrr_status hip_fail(hipError_t e, const char* what);
+
+int ilog2_floor(uint64_t x);
+
+// Resolve launch parameters (eyes per wave, stack entries) from options and
+// the tuner.
+void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes,
+                   uint32_t* epw, uint32_t* cap);
+
+// Run a set of items in one persistent launch on `stream` with scratch `S`.
+// When `sync` is false the call only enqueues work and the caller reads the
+// counters later from S.h_pinned (n_items counters, then error word, then
+// stats) after synchronising the stream.
+hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
+                        uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
+                        uint32_t* pairs, float* weights, hipStream_t stream);
+
+// Readback layout in S.h_pinned after a launch.
+inline size_t pinned_error_index(size_t n_items) { return n_items; }
+inline size_t pinned_stats_index(size_t n_items) { return n_items + 1; }
+
+void release_scratch(LaunchScratch& S);
+
+}  // namespace hrr

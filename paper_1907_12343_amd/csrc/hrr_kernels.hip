@@ -1,0 +1,660 @@
+// hrr_kernels.hip -- gfx950 kernels for hierarchical Russian roulette with a
+// rotated base-2 radical inverse (Pantaleoni, "Blue-Noise Dithered QMC
+// Hierarchical Russian Roulette").
+//
+//   rmq_kernel       one range-minimum query per lane (Section 1, v(a,b);
+//                    Section 2, Algorithms 2-3), streaming u32 arrays.
+//   traverse_kernel  persistent wavefronts that pull (item, eye group) tasks
+//                    from a device work queue and cull every eye's pairs by a
+//                    top-down walk of its item's light hierarchy (Section 1).
+//
+// Wavefront design.  One wave owns a group of 1..8 eyes.  Its stack of
+// pending hierarchy nodes lives in LDS and is shared by the 64 lanes: each
+// iteration pops up to 64 nodes (one per lane), each lane fetches its node's
+// 64-byte record (both children's boxes), derives the children's range minima
+// -- the child that contains the parent's argmin inherits it, the other needs
+// one range-minimum query -- bounds both children, and the survivors are
+// pushed back with ballot/mbcnt compaction.  Leaves with one light are tested
+// exactly at the parent; accepted pairs are staged in LDS and flushed with one
+// 64-bit atomic per chunk.  The stack spills in halves to a per-wave region
+// of device memory when it would overflow LDS; its size is bounded by
+// 128 entries per tree level (see stack_spill).
+//
+// Floating point: every acceptance probability is computed in binary32 with
+// separately rounded operations (no contraction) and an IEEE division, so that
+// a one-light leaf's test is bit-identical to the all-pairs definition.
+#include <hip/hip_runtime.h>
+
+#include "hrr_rmq.hpp"
+#include "hrr_types.hpp"
+
+#pragma clang fp contract(off)
+
+namespace hrr {
+
+// ---------------------------------------------------------------------------
+// wavefront helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+// number of set bits of m in lanes below this one
+__device__ __forceinline__ uint32_t count_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t uni(uint32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+
+__device__ __forceinline__ float unif(float x) {
+    return __uint_as_float(__builtin_amdgcn_readfirstlane(__float_as_uint(x)));
+}
+
+// Order LDS traffic of one wave across lanes: the wave executes in lock step
+// and LDS serves one wave's requests in order, so only compiler reordering
+// has to be prevented.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// acceptance bound
+// ---------------------------------------------------------------------------
+
+// squared distance from the eye to the box [lo, hi] (0 inside), summed
+// (x + y) + z; for a one-point box this is the pair's own d^2 bit for bit.
+__device__ __forceinline__ float box_d2(float ex, float ey, float ez, float lx, float ly, float lz,
+                                        float hx, float hy, float hz) {
+    const float dx = fmaxf(fmaxf(lx - ex, ex - hx), 0.0f);
+    const float dy = fmaxf(fmaxf(ly - ey, ey - hy), 0.0f);
+    const float dz = fmaxf(fmaxf(lz - ez, ez - hz), 0.0f);
+    const float x2 = dx * dx;
+    const float y2 = dy * dy;
+    const float z2 = dz * dz;
+    return (x2 + y2) + z2;
+}
+
+// p = min(1, (s / d2) * mult).  mult = 1 for an exact one-light test; for a
+// multi-light box mult = 1 + 2^-20, a safety factor on the bound (every step
+// above is monotone, so the box bound is already >= each light's p).
+__device__ __forceinline__ float accept_p(float s, float d2, float mult) {
+    float q = s / d2;
+    q = q * mult;
+    return fminf(q, 1.0f);
+}
+
+// Russian roulette with a 32-bit fixed-point random number: keep iff
+// v / 2^32 < p, i.e. v < ceil(p * 2^32) (exact: the scaling is a power of 2).
+__device__ __forceinline__ bool keeps(uint32_t v, float p) {
+    if (p >= 1.0f) return true;
+    return v < (uint32_t)ceilf(p * 4294967296.0f);
+}
+
+constexpr float kBoxMargin = 1.0f + 0x1p-20f;
+
+// Fixed-point golden-ratio lattice alpha = round(2^32 (sqrt(5) - 1) / 2).
+constexpr uint32_t kGoldenAlpha = 2654435769u;
+
+// ---------------------------------------------------------------------------
+// range-minimum kernel
+// ---------------------------------------------------------------------------
+
+template <int METHOD>
+__device__ __forceinline__ void rmq_one(uint32_t a, uint32_t b, uint32_t R, uint32_t& k, uint32_t& v,
+                                        uint32_t& bad) {
+    if (a < b) {
+        k = rmq<METHOD>(a, b, threshold_index(R));
+        v = rotated(k, R);
+    } else {
+        k = b;
+        v = 0xFFFFFFFFu;
+        ++bad;
+    }
+}
+
+// Four queries per lane per step through 16-byte loads when every array is
+// 16-byte aligned (vec != 0); the scalar tail and unaligned arrays go one
+// query at a time.
+template <int METHOD>
+__global__ __launch_bounds__(256) void rmq_kernel(const uint32_t* __restrict__ A, const uint32_t* __restrict__ B,
+                                                  const uint32_t* __restrict__ R, uint64_t n,
+                                                  uint32_t* __restrict__ K, uint32_t* __restrict__ V,
+                                                  unsigned long long* __restrict__ n_bad, int vec) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    uint32_t bad = 0;
+    uint64_t done = 0;
+    if (vec) {
+        const uint64_t n4 = n >> 2;
+        const uint4* A4 = reinterpret_cast<const uint4*>(A);
+        const uint4* B4 = reinterpret_cast<const uint4*>(B);
+        const uint4* R4 = reinterpret_cast<const uint4*>(R);
+        uint4* K4 = reinterpret_cast<uint4*>(K);
+        uint4* V4 = reinterpret_cast<uint4*>(V);
+        for (uint64_t q = tid; q < n4; q += stride) {
+            const uint4 a = A4[q];
+            const uint4 b = B4[q];
+            const uint4 r = R4[q];
+            uint4 k, v;
+            rmq_one<METHOD>(a.x, b.x, r.x, k.x, v.x, bad);
+            rmq_one<METHOD>(a.y, b.y, r.y, k.y, v.y, bad);
+            rmq_one<METHOD>(a.z, b.z, r.z, k.z, v.z, bad);
+            rmq_one<METHOD>(a.w, b.w, r.w, k.w, v.w, bad);
+            K4[q] = k;
+            V4[q] = v;
+        }
+        done = n4 << 2;
+    }
+    for (uint64_t q = done + tid; q < n; q += stride) {
+        uint32_t k, v;
+        rmq_one<METHOD>(A[q], B[q], R[q], k, v, bad);
+        K[q] = k;
+        V[q] = v;
+    }
+    if (n_bad) {
+        const uint64_t m = ballot(bad != 0);
+        if (m) {
+            // wave-reduce the few non-zero counts
+            uint32_t tot = bad;
+            for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o);
+            if (lane_id() == 0) atomicAdd(n_bad, (unsigned long long)tot);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// traversal kernel
+// ---------------------------------------------------------------------------
+
+struct EyeState {
+    float ex, ey, ez;
+    uint32_t R;     // rotation r_j (+ extras), fixed point
+    uint32_t kr;    // threshold index Phi_2^{-1}(1 - r_j)
+    uint32_t u;     // virtual eye index emitted as the pair's first component
+};
+
+// LDS of one wave: stack ring, staged pairs, staged weights, eye table.
+struct WaveLds {
+    uint2* stack;
+    uint2* stage;
+    float* wstage;
+    uint32_t* eyes;   // 8 words per slot
+};
+
+// ---- per-wave stack in LDS with spill to device memory ----
+//
+// Logical positions [0, g) live in the wave's spill region, [g, g + n) in the
+// LDS ring at position & (cap - 1).  Only whole halves (cap / 2 entries,
+// aligned) move, so a lane always re-reads exactly what it wrote.
+//
+// Size bound.  Pops take the top <= 64 entries (lanes in stack order) and
+// each pushes its surviving children next to each other, so depths never
+// decrease from bottom to top.  A pop that reaches an entry of depth d - 1
+// also removes every entry of depth >= d above it; hence all entries of depth
+// d come from one pop and number at most 128, and the stack never holds more
+// than 128 * (max depth + 1) entries.
+struct StackState {
+    uint32_t g;   // entries in device memory
+    uint32_t n;   // entries in LDS
+    uint32_t max_total;
+    uint32_t spills;
+};
+
+__device__ __forceinline__ bool stack_spill(StackState& st, const WaveLds& L, uint2* spill, uint32_t cap,
+                                            uint32_t spill_cap, uint32_t* err) {
+    const uint32_t half = cap >> 1;
+    if (st.g + half > spill_cap) {
+        if (lane_id() == 0) atomicOr(err, (uint32_t)ERR_SPILL_OVERFLOW);
+        return false;
+    }
+    wave_sync();
+    for (uint32_t t = lane_id(); t < half; t += kWave) {
+        const uint32_t pos = st.g + t;
+        spill[pos] = L.stack[pos & (cap - 1)];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    st.g += half;
+    st.n -= half;
+    ++st.spills;
+    return true;
+}
+
+__device__ __forceinline__ void stack_refill(StackState& st, const WaveLds& L, const uint2* spill, uint32_t cap) {
+    const uint32_t half = cap >> 1;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const uint32_t base = st.g - half;
+    for (uint32_t t = lane_id(); t < half; t += kWave) {
+        const uint32_t pos = base + t;
+        L.stack[pos & (cap - 1)] = spill[pos];
+    }
+    wave_sync();
+    st.g -= half;
+    st.n += half;
+    ++st.spills;
+}
+
+// ---- staged output ----
+
+__device__ __forceinline__ void stage_flush(uint32_t& staged, const WaveLds& L, const ItemDesc& D,
+                                            bool with_w) {
+    if (staged == 0) return;
+    wave_sync();
+    unsigned long long base = 0;
+    if (lane_id() == 0) base = atomicAdd(D.counter, (unsigned long long)staged);
+    base = ((unsigned long long)uni((uint32_t)(base >> 32)) << 32) | uni((uint32_t)base);
+    for (uint32_t t = lane_id(); t < staged; t += kWave) {
+        const unsigned long long pos = base + t;
+        if (pos < D.capacity) {
+            reinterpret_cast<uint2*>(D.pairs)[pos] = L.stage[t];
+            if (with_w) D.weights[pos] = L.wstage[t];
+        }
+    }
+    wave_sync();
+    staged = 0;
+}
+
+// Stage up to one pair per lane; the caller guarantees room for 64.
+__device__ __forceinline__ void stage_put(uint32_t& staged, const WaveLds& L, bool emit, uint32_t u,
+                                          uint32_t i, float w, bool with_w) {
+    const uint64_t m = ballot(emit);
+    if (emit) {
+        const uint32_t at = staged + count_below(m);
+        L.stage[at] = make_uint2(u, i);
+        if (with_w) L.wstage[at] = w;
+    }
+    staged += (uint32_t)__popcll(m);
+}
+
+__device__ __forceinline__ EyeState load_eye(const ItemDesc& D, const uint32_t* tile, uint32_t u) {
+    EyeState E;
+    const uint32_t ns = D.n_samples;
+    const uint32_t j = ns > 1 ? u / ns : u;
+    const uint32_t n = ns > 1 ? u - j * ns : 0u;
+    E.ex = D.eyes[3u * j + 0];
+    E.ey = D.eyes[3u * j + 1];
+    E.ez = D.eyes[3u * j + 2];
+    const uint32_t pix = D.pixel_base + j;
+    const uint32_t x = pix % D.width;
+    const uint32_t y = pix / D.width;
+    uint32_t R = tile[(x & 63u) * 64u + (y & 63u)] + D.shift_offset;
+    if (ns > 1) R += D.psi_s0 + n * kGoldenAlpha;
+    E.R = R;
+    E.kr = threshold_index(R);
+    E.u = u;
+    return E;
+}
+
+// Exact per-light tests of the leaf children that survived their box bound
+// and hold more than one light.  Lane-local loops; emissions are compacted
+// every step.
+template <bool W>
+__device__ __forceinline__ void leaf_lights(uint32_t& staged, const WaveLds& L, const ItemDesc& D,
+                                            const EyeState& E, uint32_t la, uint32_t ln, uint32_t ra,
+                                            uint32_t rn, uint64_t& tests) {
+    const uint32_t total = ln + rn;
+    for (uint32_t q = 0; ballot(q < total); ++q) {
+        if (staged + kWave > kStage) stage_flush(staged, L, D, W);
+        const bool act = q < total;
+        bool emit = false;
+        uint32_t i = 0;
+        float w = 0.0f;
+        if (act) {
+            i = q < ln ? la + q : ra + (q - ln);
+            const float4 P = reinterpret_cast<const float4*>(D.lights)[i];
+            const float d2 = box_d2(E.ex, E.ey, E.ez, P.x, P.y, P.z, P.x, P.y, P.z);
+            const float p = accept_p(D.s, d2, 1.0f);
+            emit = keeps(rotated(i, E.R), p);
+            if (W) w = 1.0f / p;
+            ++tests;
+        }
+        stage_put(staged, L, emit, E.u, i, w, W);
+    }
+}
+
+template <int EPW, int METHOD, bool STATS, bool W>
+__global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravArgs A) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    // dynamic LDS: task table (n_items + 1 entries, padded to 16 bytes), then one area per wave
+    uint32_t* task_begin_lds = reinterpret_cast<uint32_t*>(smem);
+    for (uint32_t t = threadIdx.x; t <= A.n_items; t += blockDim.x) task_begin_lds[t] = A.task_begin[t];
+    __syncthreads();
+    unsigned char* wave_area = smem + (((size_t)A.n_items + 1u) * sizeof(uint32_t) + 15u) / 16u * 16u;
+
+    const uint32_t lane = lane_id();
+    const uint32_t wv = threadIdx.x / kWave;
+    const uint32_t wave_gid = blockIdx.x * kWavesPerBlock + wv;
+    const uint32_t cap = A.stack_cap;
+
+    unsigned char* base = wave_area + (size_t)wv * A.lds_per_wave;
+    WaveLds L;
+    L.stack = reinterpret_cast<uint2*>(base);
+    L.stage = reinterpret_cast<uint2*>(base + (size_t)cap * sizeof(uint2));
+    L.wstage = reinterpret_cast<float*>(base + (size_t)cap * sizeof(uint2) + kStage * sizeof(uint2));
+    L.eyes = reinterpret_cast<uint32_t*>(base + (size_t)cap * sizeof(uint2) + kStage * sizeof(uint2) +
+                                         (W ? kStage * sizeof(float) : 0));
+    uint2* spill = reinterpret_cast<uint2*>(A.spill) + (size_t)wave_gid * A.spill_cap;
+
+    uint64_t st_eyes = 0, st_visits = 0, st_rmq = 0, st_leaf = 0, st_spills = 0;
+    uint32_t st_maxstack = 0;
+
+    uint32_t cur = 0xFFFFFFFFu;
+    ItemDesc D;
+    uint32_t staged = 0;
+
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(A.task_counter, 1u);
+        t = uni(t);
+        if (t >= A.n_tasks) break;
+
+        // item of task t: largest k with task_begin[k] <= t
+        uint32_t lo = 0, hi = A.n_items;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (task_begin_lds[mid] <= t) lo = mid; else hi = mid;
+        }
+        const uint32_t it = uni(lo);
+        if (it != cur) {
+            if (cur != 0xFFFFFFFFu) stage_flush(staged, L, D, W);
+            cur = it;
+            D = A.items[it];
+        }
+        const uint32_t u0 = (t - D.task_begin) * EPW;
+        const uint32_t cnt = min((uint32_t)EPW, D.n_virtual - u0);
+        const uint32_t N = D.n_lights;
+        const uint32_t leaf = D.leaf_size;
+        const float s = D.s;
+
+        // -------- eyes of this task --------
+        EyeState E0;   // EPW == 1: wave-uniform eye
+        if (EPW == 1) {
+            E0 = load_eye(D, A.tile, u0);
+            E0.ex = unif(E0.ex); E0.ey = unif(E0.ey); E0.ez = unif(E0.ez);
+            E0.R = uni(E0.R); E0.kr = uni(E0.kr);
+        } else {
+            if (lane < cnt) {
+                const EyeState e = load_eye(D, A.tile, u0 + lane);
+                uint32_t* w = L.eyes + lane * 8u;
+                w[0] = __float_as_uint(e.ex); w[1] = __float_as_uint(e.ey); w[2] = __float_as_uint(e.ez);
+                w[3] = e.R; w[4] = e.kr; w[5] = e.u;
+            }
+            wave_sync();
+        }
+        if (STATS) st_eyes += cnt;
+
+        StackState S;
+        S.g = 0; S.n = 0; S.max_total = 0; S.spills = 0;
+
+        // -------- roots --------
+        {
+            const bool act = lane < cnt;
+            EyeState E = E0;
+            if (EPW > 1 && act) {
+                const uint32_t* w = L.eyes + lane * 8u;
+                E.ex = __uint_as_float(w[0]); E.ey = __uint_as_float(w[1]); E.ez = __uint_as_float(w[2]);
+                E.R = w[3]; E.kr = w[4]; E.u = w[5];
+            }
+            if (D.n_nodes == 0) {
+                // the whole light set is one leaf: exact tests of its <= 8 lights
+                uint64_t tests = 0;
+                const uint32_t n_here = act ? N : 0u;
+                if (EPW == 1) {
+                    // spread the lights of the single eye over the lanes
+                    if (staged + kWave > kStage) stage_flush(staged, L, D, W);
+                    const bool a1 = lane < N;
+                    bool emit = false;
+                    float w = 0.0f;
+                    if (a1) {
+                        const float4 P = reinterpret_cast<const float4*>(D.lights)[lane];
+                        const float d2 = box_d2(E.ex, E.ey, E.ez, P.x, P.y, P.z, P.x, P.y, P.z);
+                        const float p = accept_p(s, d2, 1.0f);
+                        emit = keeps(rotated(lane, E.R), p);
+                        if (W) w = 1.0f / p;
+                        ++tests;
+                    }
+                    stage_put(staged, L, emit, E.u, lane, w, W);
+                } else {
+                    leaf_lights<W>(staged, L, D, E, 0u, n_here, 0u, 0u, tests);
+                }
+                if (STATS) st_leaf += tests;
+                continue;
+            }
+            bool push = false;
+            uint32_t k0 = 0;
+            if (act) {
+                k0 = rmq<METHOD>(0u, N, E.kr);
+                const float d2 = box_d2(E.ex, E.ey, E.ez, D.root_lo[0], D.root_lo[1], D.root_lo[2],
+                                        D.root_hi[0], D.root_hi[1], D.root_hi[2]);
+                push = keeps(rotated(k0, E.R), accept_p(s, d2, kBoxMargin));
+                if (STATS) ++st_rmq;
+            }
+            const uint64_t m = ballot(push);
+            if (push) {
+                const uint32_t at = count_below(m);
+                L.stack[at] = make_uint2(0u | ((EPW > 1 ? lane : 0u) << kSlotShift), k0);
+            }
+            S.n = (uint32_t)__popcll(m);
+            wave_sync();
+        }
+
+        // -------- top-down walk --------
+        while (S.n + S.g > 0) {
+            if (S.n < kWave && S.g > 0) stack_refill(S, L, spill, cap);
+            const uint32_t n = min(S.n, (uint32_t)kWave);
+            const uint32_t top = S.g + S.n;
+            const bool act = lane < n;
+            uint2 e = make_uint2(0u, 0u);
+            if (act) e = L.stack[(top - n + lane) & (cap - 1)];
+            S.n -= n;
+            wave_sync();
+            if (STATS) st_visits += n;
+
+            EyeState E = E0;
+            const uint32_t node = e.x & (kMaxNodes - 1u);
+            const uint32_t slot = e.x >> kSlotShift;
+            if (EPW > 1 && act) {
+                const uint32_t* w = L.eyes + slot * 8u;
+                E.ex = __uint_as_float(w[0]); E.ey = __uint_as_float(w[1]); E.ez = __uint_as_float(w[2]);
+                E.R = w[3]; E.kr = w[4]; E.u = w[5];
+            }
+
+            bool pushL = false, pushR = false, emitL = false, emitR = false;
+            uint32_t kL = 0, kR = 0, a = 0, c = 0, b = 0, rightIdx = 0;
+            uint32_t mlA = 0, mlN = 0, mrA = 0, mrN = 0;   // multi-light leaf ranges to test
+            float wL = 0.0f, wR = 0.0f;
+            if (act) {
+                const float4* rec = reinterpret_cast<const float4*>(D.nodes + node);
+                const float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3];
+                a = __float_as_uint(q0.w);
+                c = __float_as_uint(q1.w);
+                b = __float_as_uint(q2.w);
+                rightIdx = __float_as_uint(q3.w);
+                const uint32_t k = e.y;
+                // the child holding k inherits the minimum; the other one needs a query
+                const bool kLeft = k < c;
+                const uint32_t qa = kLeft ? c : a;
+                const uint32_t qb = kLeft ? b : c;
+                uint32_t kq = qa;
+                if (qb - qa > 1u) {
+                    kq = rmq<METHOD>(qa, qb, E.kr);
+                    if (STATS) ++st_rmq;
+                }
+                kL = kLeft ? k : kq;
+                kR = kLeft ? kq : k;
+                const uint32_t nL = c - a, nR = b - c;
+                const bool leafL = nL <= leaf, leafR = nR <= leaf;
+                const float d2L = box_d2(E.ex, E.ey, E.ez, q0.x, q0.y, q0.z, q1.x, q1.y, q1.z);
+                const float d2R = box_d2(E.ex, E.ey, E.ez, q2.x, q2.y, q2.z, q3.x, q3.y, q3.z);
+                const float pL = accept_p(s, d2L, nL == 1u ? 1.0f : kBoxMargin);
+                const float pR = accept_p(s, d2R, nR == 1u ? 1.0f : kBoxMargin);
+                const bool sL = keeps(rotated(kL, E.R), pL);
+                const bool sR = keeps(rotated(kR, E.R), pR);
+                pushL = sL && !leafL;
+                pushR = sR && !leafR;
+                emitL = sL && nL == 1u;
+                emitR = sR && nR == 1u;
+                if (W) { wL = 1.0f / pL; wR = 1.0f / pR; }
+                if (sL && leafL && nL > 1u) { mlA = a; mlN = nL; }
+                if (sR && leafR && nR > 1u) { mrA = c; mrN = nR; }
+                if (STATS) st_leaf += (uint64_t)(nL == 1u) + (uint64_t)(nR == 1u);
+            }
+
+            // push survivors: a lane's two children stay adjacent, lanes in order
+            const uint64_t bl = ballot(pushL), br = ballot(pushR);
+            const uint32_t npush = (uint32_t)(__popcll(bl) + __popcll(br));
+            if (npush) {
+                if (S.n + npush > cap) {
+                    if (!stack_spill(S, L, spill, cap, A.spill_cap, A.error)) break;
+                }
+                const uint32_t at = S.g + S.n + count_below(bl) + count_below(br);
+                const uint32_t tag = (EPW > 1 ? slot : 0u) << kSlotShift;
+                if (pushL) L.stack[at & (cap - 1)] = make_uint2((node + 1u) | tag, kL);
+                if (pushR) L.stack[(at + (pushL ? 1u : 0u)) & (cap - 1)] = make_uint2(rightIdx | tag, kR);
+                S.n += npush;
+                wave_sync();
+                const uint32_t tot = S.g + S.n;
+                if (tot > S.max_total) S.max_total = tot;
+            }
+
+            // one-light leaves accepted at the parent
+            if (staged + 2u * kWave > kStage) stage_flush(staged, L, D, W);
+            stage_put(staged, L, emitL, E.u, a, wL, W);
+            stage_put(staged, L, emitR, E.u, c, wR, W);
+
+            // multi-light leaves
+            if (ballot(mlN + mrN > 0u)) {
+                uint64_t tests = 0;
+                leaf_lights<W>(staged, L, D, E, mlA, mlN, mrA, mrN, tests);
+                if (STATS) st_leaf += tests;
+            }
+        }
+        if (STATS) {
+            st_spills += S.spills;
+            st_maxstack = max(st_maxstack, S.max_total);
+        }
+    }
+    if (cur != 0xFFFFFFFFu) stage_flush(staged, L, D, W);
+
+    if (STATS && A.stats) {
+        uint64_t v[6] = {st_eyes, 0, st_visits, st_rmq, st_leaf, st_spills};
+        for (int q = 0; q < 6; ++q) {
+            uint64_t x = v[q];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+            v[q] = x;
+        }
+        uint32_t mx = st_maxstack;
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o));
+        if (lane == 0) {
+            // eyes / spills / max stack are per-wave quantities kept in every lane
+            atomicAdd(A.stats + ST_EYES, (unsigned long long)(v[0] / kWave));
+            atomicAdd(A.stats + ST_VISITS, (unsigned long long)(v[2] / kWave));
+            atomicAdd(A.stats + ST_RMQ, (unsigned long long)v[3]);
+            atomicAdd(A.stats + ST_LEAF, (unsigned long long)v[4]);
+            atomicAdd(A.stats + ST_SPILLS, (unsigned long long)(v[5] / kWave));
+            atomicMax(A.stats + ST_MAXSTACK, (unsigned long long)mx);
+        }
+    }
+}
+
+}  // namespace hrr
+
+// ---------------------------------------------------------------------------
+// launchers (called from the C++ runtime)
+// ---------------------------------------------------------------------------
+
+extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const uint32_t* r, uint64_t n,
+                                     uint32_t method, uint32_t* k, uint32_t* v, unsigned long long* n_bad,
+                                     int n_cu, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const int vec = ((((uintptr_t)a) | ((uintptr_t)b) | ((uintptr_t)r) | ((uintptr_t)k) | ((uintptr_t)v)) & 15u) == 0;
+    const uint64_t work = vec ? (n + 3) / 4 : n;
+    uint64_t blocks = (work + 255) / 256;
+    const uint64_t max_blocks = (uint64_t)(n_cu > 0 ? n_cu : 256) * 16;
+    if (blocks > max_blocks) blocks = max_blocks;
+    if (blocks < 1) blocks = 1;
+    if (method == 1)
+        hipLaunchKernelGGL(hrr::rmq_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
+    else
+        hipLaunchKernelGGL(hrr::rmq_kernel<0>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
+    return hipGetLastError();
+}
+
+namespace {
+
+template <int EPW, int METHOD, bool STATS, bool W>
+hipError_t launch_trav(const hrr::TravArgs& A, uint32_t blocks, size_t lds, hipStream_t stream) {
+    auto kern = hrr::traverse_kernel<EPW, METHOD, STATS, W>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(hrr::kWave * hrr::kWavesPerBlock), lds, stream, A);
+    return hipGetLastError();
+}
+
+template <int EPW, int METHOD, bool STATS>
+hipError_t pick_w(const hrr::TravArgs& A, bool w, uint32_t blocks, size_t lds, hipStream_t s) {
+    return w ? launch_trav<EPW, METHOD, STATS, true>(A, blocks, lds, s)
+             : launch_trav<EPW, METHOD, STATS, false>(A, blocks, lds, s);
+}
+
+template <int EPW, int METHOD>
+hipError_t pick_stats(const hrr::TravArgs& A, bool st, bool w, uint32_t blocks, size_t lds, hipStream_t s) {
+    return st ? pick_w<EPW, METHOD, true>(A, w, blocks, lds, s) : pick_w<EPW, METHOD, false>(A, w, blocks, lds, s);
+}
+
+template <int EPW>
+hipError_t pick_method(const hrr::TravArgs& A, uint32_t method, bool st, bool w, uint32_t blocks, size_t lds,
+                       hipStream_t s) {
+    return method == 1 ? pick_stats<EPW, 1>(A, st, w, blocks, lds, s) : pick_stats<EPW, 0>(A, st, w, blocks, lds, s);
+}
+
+}  // namespace
+
+// LDS bytes of one wave for a given stack size.
+extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap, int with_weights) {
+    return (size_t)stack_cap * sizeof(uint2) + hrr::kStage * sizeof(uint2) +
+           (with_weights ? hrr::kStage * sizeof(float) : 0) + 8 * 8 * sizeof(uint32_t);
+}
+
+// Dynamic LDS bytes of one block.
+extern "C" size_t hrr_trav_lds_per_block(uint32_t n_items, size_t lds_per_wave) {
+    return ((size_t)n_items + 1u) * sizeof(uint32_t) / 16u * 16u + 16u + lds_per_wave * hrr::kWavesPerBlock;
+}
+
+extern "C" hipError_t hrr_launch_traverse(const hrr::TravArgs* A, uint32_t eyes_per_wave, uint32_t method,
+                                          int stats, int with_weights, uint32_t blocks, hipStream_t stream) {
+    const size_t lds = hrr_trav_lds_per_block(A->n_items, A->lds_per_wave);
+    switch (eyes_per_wave) {
+        case 1: return pick_method<1>(*A, method, stats, with_weights, blocks, lds, stream);
+        case 2: return pick_method<2>(*A, method, stats, with_weights, blocks, lds, stream);
+        case 4: return pick_method<4>(*A, method, stats, with_weights, blocks, lds, stream);
+        case 8: return pick_method<8>(*A, method, stats, with_weights, blocks, lds, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// Resident blocks per CU for a launch shape (for sizing the persistent grid).
+extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t method, int stats, int with_weights,
+                                             size_t lds_per_block, int* blocks_per_cu) {
+    const void* f = nullptr;
+#define HRR_PICK(E, M, S, W) \
+    if (eyes_per_wave == E && method == M && (stats != 0) == S && (with_weights != 0) == W) \
+        f = (const void*)hrr::traverse_kernel<E, M, S, W>;
+#define HRR_PICK_SW(E, M) HRR_PICK(E, M, false, false) HRR_PICK(E, M, false, true) HRR_PICK(E, M, true, false) HRR_PICK(E, M, true, true)
+#define HRR_PICK_M(E) HRR_PICK_SW(E, 0) HRR_PICK_SW(E, 1)
+    HRR_PICK_M(1) HRR_PICK_M(2) HRR_PICK_M(4) HRR_PICK_M(8)
+#undef HRR_PICK_M
+#undef HRR_PICK_SW
+#undef HRR_PICK
+    if (!f) return hipErrorInvalidValue;
+    if (lds_per_block > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_per_block);
+        if (e != hipSuccess) return e;
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, hrr::kWave * hrr::kWavesPerBlock,
+                                                        lds_per_block);
+}

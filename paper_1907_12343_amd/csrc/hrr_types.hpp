@@ -1,0 +1,75 @@
+// hrr_types.hpp -- data layouts shared by the library's host code and its
+// gfx950 kernels (not by the oracle).
+#pragma once
+
+#include <stdint.h>
+
+namespace hrr {
+
+// One internal node of the light hierarchy, 64 bytes (half a 128-byte cache
+// line).  The node covers sequence indices [a, b) (Section 1: a node is a
+// contiguous sub-range of the sorted lights) and is split at c into
+// [a, c) and [c, b).  It stores the fp32 bounding boxes of BOTH children, so
+// one 64-byte fetch lets a lane bound and cull two subtrees.  Internal nodes
+// are numbered in depth-first preorder: the left child, when internal, is
+// this node + 1; `right` is the right child's number when internal.  A child
+// whose range has at most leaf_size lights is a leaf and has no record.
+struct alignas(64) Node {
+    float lo_l[3];
+    uint32_t a;
+    float hi_l[3];
+    uint32_t c;
+    float lo_r[3];
+    uint32_t b;
+    float hi_r[3];
+    uint32_t right;
+};
+static_assert(sizeof(Node) == 64, "node record must be 64 bytes");
+
+// Device-side description of one traversal work item (one hierarchy, one
+// eye set, one output slice).  Eyes are "virtual": with N samples per pair,
+// virtual eye u is eye u / N, sample u % N.
+struct ItemDesc {
+    const Node* nodes;
+    const float* lights;          // 4 floats per light (x, y, z, 0), sequence order
+    const float* eyes;            // 3 floats per eye
+    uint32_t* pairs;              // item's output slice, 2 u32 per pair
+    float* weights;               // item's weight slice or null
+    unsigned long long* counter;  // item's pair counter (device)
+    unsigned long long capacity;  // pairs the slice can hold
+    uint32_t n_lights, n_nodes, leaf_size, n_virtual;
+    uint32_t width, shift_offset, pixel_base, n_samples;
+    uint32_t psi_s0, task_begin;
+    float s;
+    float root_lo[3], root_hi[3];
+    uint32_t pad[3];
+};
+
+// Kernel arguments of the persistent traversal launch.
+struct TravArgs {
+    const ItemDesc* items;
+    const uint32_t* task_begin;   // n_items + 1 prefix of tasks per item
+    uint32_t n_items, n_tasks;
+    uint32_t* task_counter;       // device work queue head
+    const uint32_t* tile;         // 64 x 64 shifts
+    unsigned long long* spill;    // per-wave spill stacks (uint2 entries)
+    uint32_t spill_cap;           // entries per wave
+    uint32_t stack_cap;           // LDS stack entries per wave (power of two)
+    uint32_t lds_per_wave;        // bytes
+    uint32_t pad0;
+    unsigned long long* stats;    // 8 counters or null
+    uint32_t* error;              // set non-zero on an internal failure
+};
+
+constexpr int kWave = 64;
+constexpr int kWavesPerBlock = 4;
+constexpr uint32_t kStage = 512;        // staged pairs per wave before a flush
+constexpr uint32_t kMaxItemsPerLaunch = 1024;
+constexpr uint32_t kSlotShift = 28;     // stack entry: node | slot << 28
+constexpr uint32_t kMaxNodes = 1u << kSlotShift;
+
+enum StatIdx { ST_EYES = 0, ST_PAIRS, ST_VISITS, ST_RMQ, ST_LEAF, ST_SPILLS, ST_MAXSTACK, ST_N };
+
+enum ErrCode { ERR_NONE = 0, ERR_SPILL_OVERFLOW = 1 };
+
+}  // namespace hrr

@@ -1,0 +1,54 @@
+"""Shared helpers of the GPU parity tests (test code; not collected)."""
+import numpy as np
+
+M32 = 0xFFFFFFFF
+
+
+def pair_keys_from_gpu(pairs_t, n_virtual_per_key=1):
+    """(n, 2) int32 cuda tensor of (u, i) -> sorted numpy uint64 keys (u << 32) | i."""
+    import torch
+    if pairs_t.shape[0] == 0:
+        return np.zeros(0, np.uint64)
+    u = pairs_t[:, 0].to(torch.int64) & M32
+    i = pairs_t[:, 1].to(torch.int64) & M32
+    k = torch.sort((u << 32) | i).values
+    return k.cpu().numpy().view(np.uint64)
+
+
+def pair_keys_from_oracle(out, sel, n_samples=1):
+    """oracle.accept_eyes(..., lists=True) result -> sorted uint64 keys."""
+    off = out["offsets"]
+    idx = out["idx"].astype(np.uint64)
+    smp = out["sample"].astype(np.uint64)
+    cnt = np.diff(off).astype(np.int64)
+    j = np.repeat(np.asarray(sel, np.uint64), cnt)
+    u = j * np.uint64(n_samples) + smp
+    return np.sort((u << np.uint64(32)) | idx)
+
+
+def select_pairs_of_eyes(pairs_t, sel, chunk=1 << 27):
+    """Pairs (u, i) of the eyes u in sel, from a possibly huge tensor, as keys."""
+    import torch
+    dev = pairs_t.device
+    sel_t = torch.as_tensor(np.asarray(sel, np.int64), device=dev)
+    parts = []
+    for s in range(0, pairs_t.shape[0], chunk):
+        blk = pairs_t[s:s + chunk]
+        u = blk[:, 0].to(torch.int64) & M32
+        m = torch.isin(u, sel_t)
+        if m.any():
+            i = blk[:, 1].to(torch.int64) & M32
+            parts.append((u[m] << 32) | i[m])
+    if not parts:
+        return np.zeros(0, np.uint64)
+    k = torch.sort(torch.cat(parts)).values
+    return k.cpu().numpy().view(np.uint64)
+
+
+def per_eye_counts(pairs_t, n_eyes, chunk=1 << 27):
+    import torch
+    cnt = torch.zeros(n_eyes, dtype=torch.int64, device=pairs_t.device)
+    for s in range(0, pairs_t.shape[0], chunk):
+        u = pairs_t[s:s + chunk, 0].to(torch.int64) & M32
+        cnt += torch.bincount(u, minlength=n_eyes)
+    return cnt.cpu().numpy()

@@ -1,0 +1,249 @@
+"""GPU parity of hrr_traverse against the all-pairs oracle.
+
+The accepted (j, i) set must equal, element for element after sorting, the
+set of pairs whose own rotated radical inverse passes their own acceptance
+test (Section 1's hierarchical Russian roulette must never drop or add a
+pair).  Bit-exact: xi is an integer and the fp32 acceptance test uses the
+same rounding on both sides.
+"""
+import numpy as np
+import pytest
+
+import synth
+from _helpers import (pair_keys_from_gpu, pair_keys_from_oracle, per_eye_counts,
+                      select_pairs_of_eyes)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1907_12343_amd as hrr
+    c = hrr.Context(synth.dither_tile(100))
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return synth.tiny()
+
+
+@pytest.fixture(scope="module")
+def tiny_oracle(orc, tiny):
+    perm = orc.morton_order(tiny["lights"])
+    ls = tiny["lights"][perm]
+    sel = np.arange(tiny["eyes"].shape[0])
+    out = orc.accept_eyes(tiny["eyes"], sel, tiny["width"], 0, tiny["tile"], ls, tiny["s"],
+                          lists=True)
+    return dict(perm=perm, lights_sorted=ls, keys=pair_keys_from_oracle(out, sel), out=out)
+
+
+def _eyes_t(ctx, eyes):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(eyes, np.float32)).to(ctx.torch_device)
+
+
+def test_light_order_matches_oracle(ctx, orc, tiny, tiny_oracle):
+    for leaf in (1, 2, 4, 8):
+        h = ctx.build_hierarchy(tiny["lights"], leaf_size=leaf)
+        assert np.array_equal(h.permutation(), tiny_oracle["perm"])
+        assert np.array_equal(h.sorted_lights(), tiny_oracle["lights_sorted"])
+        h.free()
+
+
+@pytest.mark.parametrize("method", [0, 1])
+@pytest.mark.parametrize("leaf", [1, 2, 4, 8])
+@pytest.mark.parametrize("epw", [1, 2, 4, 8])
+def test_tiny_full_parity(ctx, tiny, tiny_oracle, method, leaf, epw):
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=leaf)
+    eyes = _eyes_t(ctx, tiny["eyes"])
+    pairs, n, st = ctx.traverse_all(h, eyes, tiny["s"], tiny["width"], rmq_method=method,
+                                    eyes_per_wave=epw, stack_entries=512, stats=True)
+    got = pair_keys_from_gpu(pairs)
+    assert n == tiny_oracle["keys"].size
+    assert np.array_equal(got, tiny_oracle["keys"])
+    assert st["eyes"] == tiny["eyes"].shape[0]
+    h.free()
+
+
+def test_stack_spills_to_device_memory(ctx, orc):
+    # a wide survivor front (large s) against a 256-entry LDS stack
+    lights = synth.uniform_points(1 << 15, 801)
+    eyes = synth.uniform_points(512, 802)
+    tile = synth.dither_tile(100)
+    s = 2e-2
+    h = ctx.build_hierarchy(lights, leaf_size=1)
+    pairs, n, st = ctx.traverse_all(h, _eyes_t(ctx, eyes), s, 64, stack_entries=256,
+                                    eyes_per_wave=1, stats=True)
+    assert st["spills"] > 0, st
+    assert st["max_stack"] > 256
+    assert st["max_stack"] <= 128 * (h.depth + 1)
+    sel = np.arange(0, 512, 5)
+    out = orc.accept_eyes(eyes, sel, 64, 0, tile, h.sorted_lights(), s, lists=True)
+    assert np.array_equal(select_pairs_of_eyes(pairs, sel), pair_keys_from_oracle(out, sel))
+    # same set with a roomy stack and several eyes per wave
+    p2, n2, st2 = ctx.traverse_all(h, _eyes_t(ctx, eyes), s, 64, stack_entries=2048,
+                                   eyes_per_wave=4, stats=True)
+    assert n2 == n
+    assert np.array_equal(pair_keys_from_gpu(p2), pair_keys_from_gpu(pairs))
+    h.free()
+
+
+@pytest.mark.parametrize("leaf", [1, 4])
+def test_weights_are_exact_reciprocals(ctx, orc, tiny, tiny_oracle, leaf):
+    import torch
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=leaf)
+    eyes = _eyes_t(ctx, tiny["eyes"])
+    pairs, n, st, w = ctx.traverse_all(h, eyes, tiny["s"], tiny["width"], with_weights=True)
+    pj = pairs.cpu().numpy().view(np.uint32)
+    wn = w.cpu().numpy()
+    ls = tiny_oracle["lights_sorted"]
+    rng = np.random.default_rng(5)
+    pick = rng.choice(n, size=min(n, 3000), replace=False)
+    for q in pick:
+        j, i = pj[q]
+        exp = orc.accept_weight(tiny["eyes"][j], ls[i], tiny["s"])
+        assert np.float32(wn[q]) == np.float32(exp)
+    h.free()
+
+
+def test_multi_sample(ctx, orc, tiny, tiny_oracle):
+    ns, s0 = 3, 0x51ED270B
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=1)
+    eyes = _eyes_t(ctx, tiny["eyes"])
+    pairs, n, _ = ctx.traverse_all(h, eyes, tiny["s"], tiny["width"], n_samples=ns, psi_s0=s0)
+    sel = np.arange(tiny["eyes"].shape[0])
+    out = orc.accept_eyes(tiny["eyes"], sel, tiny["width"], 0, tiny["tile"],
+                          tiny_oracle["lights_sorted"], tiny["s"], n_samples=ns, psi_s0=s0,
+                          lists=True)
+    assert np.array_equal(pair_keys_from_gpu(pairs), pair_keys_from_oracle(out, sel, ns))
+    h.free()
+
+
+def test_shift_offset_and_pixel_base(ctx, orc, tiny, tiny_oracle):
+    off, base, W = 0x9E3779B9, 37, 50
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=2)
+    ne = tiny["eyes"].shape[0]
+    pairs, n, _ = ctx.traverse_all(h, _eyes_t(ctx, tiny["eyes"]), tiny["s"], W,
+                                   shift_offset=off, pixel_base=base)
+    # the oracle places eye j at pixel j: pad the eye array by `base`
+    padded = np.concatenate([np.zeros((base, 3), np.float32), tiny["eyes"]])
+    sel = np.arange(base, base + ne)
+    out = orc.accept_eyes(padded, sel, W, off, tiny["tile"], tiny_oracle["lights_sorted"],
+                          tiny["s"], lists=True)
+    exp = pair_keys_from_oracle(out, sel)
+    exp = np.sort(exp - (np.uint64(base) << np.uint64(32)))
+    assert np.array_equal(pair_keys_from_gpu(pairs), exp)
+    h.free()
+
+
+def test_overflow_reports_true_count(ctx, tiny, tiny_oracle):
+    import paper_1907_12343_amd as hrr
+    import torch
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=1)
+    eyes = _eyes_t(ctx, tiny["eyes"])
+    total = tiny_oracle["keys"].size
+    cap = total // 3
+    buf = torch.full((cap, 2), -1, dtype=torch.int32, device=ctx.torch_device)
+    with pytest.raises(hrr.OverflowResult) as ei:
+        ctx.traverse(h, eyes, tiny["s"], tiny["width"], pairs=buf)
+    assert str(total) in str(ei.value)
+    assert ctx.count(h, eyes, tiny["s"], tiny["width"]) == total
+    stored = pair_keys_from_gpu(buf)
+    assert stored.size == cap and np.unique(stored).size == cap
+    assert np.isin(stored, tiny_oracle["keys"]).all()
+    h.free()
+
+
+@pytest.mark.parametrize("n_l,leaf", [(1, 1), (2, 1), (3, 1), (5, 8), (8, 8), (9, 8), (17, 4)])
+def test_small_and_root_leaf_hierarchies(ctx, orc, n_l, leaf):
+    lights = synth.uniform_points(n_l, 900 + n_l)
+    eyes = synth.uniform_points(300, 901)
+    eyes[7] = lights[0]                      # eye on a light: d = 0, p = 1
+    tile = synth.dither_tile(100)
+    h = ctx.build_hierarchy(lights, leaf_size=leaf)
+    for epw in (1, 8):
+        pairs, n, _ = ctx.traverse_all(h, _eyes_t(ctx, eyes), 0.05, 64, eyes_per_wave=epw)
+        sel = np.arange(300)
+        out = orc.accept_eyes(eyes, sel, 64, 0, tile, h.sorted_lights(), 0.05, lists=True)
+        assert np.array_equal(pair_keys_from_gpu(pairs), pair_keys_from_oracle(out, sel))
+    h.free()
+
+
+def test_coincident_lights_split_at_midpoint(ctx, orc):
+    base = synth.uniform_points(40, 950)
+    lights = np.repeat(base, 25, axis=0)            # 25 copies each: equal Morton codes
+    eyes = synth.uniform_points(200, 951)
+    tile = synth.dither_tile(100)
+    h = ctx.build_hierarchy(lights, leaf_size=1)
+    assert np.array_equal(h.permutation(), orc.morton_order(lights))
+    pairs, n, _ = ctx.traverse_all(h, _eyes_t(ctx, eyes), 0.01, 16)
+    sel = np.arange(200)
+    out = orc.accept_eyes(eyes, sel, 16, 0, tile, h.sorted_lights(), 0.01, lists=True)
+    assert np.array_equal(pair_keys_from_gpu(pairs), pair_keys_from_oracle(out, sel))
+    h.free()
+
+
+def test_empty_inputs(ctx, tiny):
+    import torch
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=1)
+    e0 = torch.empty((0, 3), dtype=torch.float32, device=ctx.torch_device)
+    pairs, n, _ = ctx.traverse(h, e0, 1e-3, 64, capacity=16)
+    assert n == 0
+    h0 = ctx.build_hierarchy(np.zeros((0, 3), np.float32))
+    pairs, n, _ = ctx.traverse(h0, _eyes_t(ctx, tiny["eyes"]), 1e-3, 64, capacity=16)
+    assert n == 0
+    h.free()
+    h0.free()
+
+
+def test_invalid_arguments(ctx, tiny):
+    import paper_1907_12343_amd as hrr
+    with pytest.raises(hrr.HrrError):
+        ctx.build_hierarchy(np.array([[0.0, np.nan, 0.0]], np.float32))
+    with pytest.raises(hrr.HrrError):
+        ctx.build_hierarchy(tiny["lights"], leaf_size=9)
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=1)
+    e = _eyes_t(ctx, tiny["eyes"])
+    for bad_s in (0.0, -1.0, float("inf"), float("nan")):
+        with pytest.raises(hrr.HrrError):
+            ctx.traverse(h, e, bad_s, 64, capacity=8)
+    with pytest.raises(hrr.HrrError):
+        ctx.traverse(h, e, 1e-3, 0, capacity=8)
+    with pytest.raises(hrr.HrrError):
+        ctx.traverse(h, e, 1e-3, 64, capacity=8, eyes_per_wave=3)
+    with pytest.raises(hrr.HrrError):
+        ctx.traverse(h, e, 1e-3, 64, capacity=8, stack_entries=300)
+    h.free()
+
+
+def test_frame_scale_sampled(ctx, orc):
+    """1920x1080 eyes against 2^20 Gaussian-mixture lights in one launch (the
+    benchmark shape); sampled eyes compared pair for pair with the oracle, and
+    per-eye counts identical between the paper's sweep and the O(1) ablation."""
+    import torch
+    fr = synth.frame()
+    h = ctx.build_hierarchy(fr["lights"], leaf_size=1)
+    perm = orc.morton_order(fr["lights"])
+    assert np.array_equal(h.permutation(), perm)
+    eyes = _eyes_t(ctx, fr["eyes"])
+    n_eyes = fr["eyes"].shape[0]
+    n = ctx.count(h, eyes, fr["s"], fr["width"])
+    pairs, n1, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n)
+    assert n1 == n
+    sel = np.unique(np.concatenate([np.arange(0, n_eyes, 1021), [n_eyes - 1]]))
+    out = orc.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], fr["lights"][perm],
+                          fr["s"], lists=True)
+    assert np.array_equal(select_pairs_of_eyes(pairs, sel), pair_keys_from_oracle(out, sel))
+    c0 = per_eye_counts(pairs, n_eyes)
+    assert int(c0.sum()) == n
+    assert np.array_equal(c0[sel], out["count"].astype(np.int64))
+    del pairs
+    torch.cuda.empty_cache()
+    p2, n2, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n, rmq_method=1)
+    assert n2 == n
+    assert np.array_equal(per_eye_counts(p2, n_eyes), c0)
+    del p2
+    torch.cuda.empty_cache()
+    h.free()
