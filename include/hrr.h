@@ -87,8 +87,10 @@ int hrr_version(void);
 /* Range minimum of the rotated radical inverse                               */
 /* ------------------------------------------------------------------------- */
 
-#define HRR_RMQ_PAPER 0u   /* the paper's sweep (Section 2, Algorithms 2 and 3) */
+#define HRR_RMQ_PAPER 0u   /* the paper's sweeps (Section 2, Algorithms 2 and 3), refining only the
+                              candidate whose prefix class meets the range (default) */
 #define HRR_RMQ_DIRECT 1u  /* same case analysis, each sweep resolved in O(1) bit arithmetic (ablation) */
+#define HRR_RMQ_PAPER_FULL 2u /* the paper's sweeps refining every candidate in turn (ablation) */
 
 /* For q < n: k = argmin over i in [a[q], b[q]) of (bit_reverse32(i) + r[q])
  * mod 2^32 and v = that minimum (Section 1, v(a,b); Section 2, the argmin
@@ -160,7 +162,7 @@ typedef struct hrr_eyes {
 typedef struct hrr_traverse_opts {
     uint32_t eyes_per_wave; /* 0 = autotuned; else 1, 2, 4 or 8 eyes share one wavefront */
     uint32_t stack_entries; /* 0 = autotuned; else LDS stack entries per wave, power of two in [256, 4096] */
-    uint32_t rmq_method;    /* HRR_RMQ_PAPER (default) or HRR_RMQ_DIRECT */
+    uint32_t rmq_method;    /* HRR_RMQ_PAPER (default), HRR_RMQ_DIRECT or HRR_RMQ_PAPER_FULL */
     uint32_t n_samples;     /* 0 or 1 = one sample per pair; > 1: Section 3 multi-sample */
     uint32_t psi_s0;        /* start of the golden-ratio lattice psi(n) = s0 + n * alpha mod 1 */
     uint32_t flags;         /* HRR_F_* */

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libhrr.so")
 
 HRR_OK, HRR_E_INVALID, HRR_E_NOMEM, HRR_E_OVERFLOW = 0, 1, 2, 3
 HRR_E_DEVICE, HRR_E_NOTREADY, HRR_E_CANCELLED, HRR_E_BUSY = 4, 5, 6, 7
-RMQ_PAPER, RMQ_DIRECT = 0, 1
+RMQ_PAPER, RMQ_DIRECT, RMQ_PAPER_FULL = 0, 1, 2
 F_STATS = 1
 
 _u32, _u64, _i32, _f32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_float

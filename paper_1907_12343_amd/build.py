@@ -27,6 +27,7 @@ HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-pthread"
 SOURCES = [
     ("hrr_kernels.hip", DEVICE),
     ("hrr_api.cpp", HOST),
+    ("hrr_launch.cpp", HOST),
     ("hrr_build.cpp", HOST),
     ("hrr_serve.cpp", HOST),
 ]

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -19,12 +20,6 @@
 extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const uint32_t* r, uint64_t n,
                                      uint32_t method, uint32_t* k, uint32_t* v, unsigned long long* n_bad,
                                      int n_cu, hipStream_t stream);
-extern "C" hipError_t hrr_launch_traverse(const hrr::TravArgs* A, uint32_t eyes_per_wave, uint32_t method,
-                                          int stats, int with_weights, uint32_t blocks, hipStream_t stream);
-extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap, int with_weights);
-extern "C" size_t hrr_trav_lds_per_block(uint32_t n_items, size_t lds_per_wave);
-extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t method, int stats, int with_weights,
-                                             size_t lds_per_block, int* blocks_per_cu);
 
 namespace hrr {
 
@@ -86,12 +81,14 @@ void release_scratch(LaunchScratch& S) {
     S.counters.release();
     S.misc.release();
     S.spill.release();
+    S.partials.release();
+    S.slack_pairs.release();
+    S.slack_weights.release();
+    S.segments.release();
     if (S.h_pinned) (void)hipHostFree(S.h_pinned);
     S.h_pinned = nullptr;
     S.h_pinned_n = 0;
 }
-
-static bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
 void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes, uint32_t* epw,
                    uint32_t* cap) {
@@ -125,138 +122,6 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
     }
     *epw = e;
     *cap = c;
-}
-
-hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
-                        uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
-                        uint32_t* pairs, float* weights, hipStream_t stream) {
-    const size_t n = items.size();
-    if (n == 0 || n > kMaxItemsPerLaunch) return fail(HRR_E_INVALID, "items per launch must be in [1, %u]", kMaxItemsPerLaunch);
-    if (!(epw == 1 || epw == 2 || epw == 4 || epw == 8)) return fail(HRR_E_INVALID, "eyes_per_wave must be 1, 2, 4 or 8");
-    if (!is_pow2(cap) || cap < 256 || cap > 4096) return fail(HRR_E_INVALID, "stack_entries must be a power of two in [256, 4096]");
-    if (method > 1) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
-    if (n_samples == 0) n_samples = 1;
-
-    S.h_items.assign(n, ItemDesc{});
-    S.h_task_begin.assign(n + 1, 0);
-    uint64_t tasks = 0;
-    uint32_t dmax = 0;
-
-    hipError_t e;
-    if ((e = S.counters.ensure(n * sizeof(unsigned long long))) != hipSuccess) return hip_fail(e, "counters");
-    if ((e = S.misc.ensure(16 * sizeof(unsigned long long))) != hipSuccess) return hip_fail(e, "misc");
-    unsigned long long* d_counters = static_cast<unsigned long long*>(S.counters.p);
-    unsigned long long* d_misc = static_cast<unsigned long long*>(S.misc.p);
-
-    for (size_t k = 0; k < n; ++k) {
-        const HostItem& it = items[k];
-        const hrr_hierarchy* h = it.h;
-        if (!h) return fail(HRR_E_INVALID, "item %zu: null hierarchy", k);
-        if (h->owner != ctx) return fail(HRR_E_INVALID, "item %zu: hierarchy belongs to another context", k);
-        if (!(it.s > 0.0f) || !isfinite(it.s)) return fail(HRR_E_INVALID, "item %zu: s must be finite and > 0", k);
-        if (it.eyes.n > 0 && !it.eyes.xyz) return fail(HRR_E_INVALID, "item %zu: null eye positions", k);
-        if (it.eyes.width == 0) return fail(HRR_E_INVALID, "item %zu: width must be >= 1", k);
-        if (it.out_capacity > 0 && !pairs) return fail(HRR_E_INVALID, "item %zu: null pairs buffer", k);
-        const uint64_t nv = (uint64_t)it.eyes.n * n_samples;
-        if (nv > 0xFFFFFFFFull) return fail(HRR_E_INVALID, "item %zu: eyes x samples exceeds 2^32 - 1", k);
-        ItemDesc& D = S.h_items[k];
-        D.nodes = h->d_nodes;
-        D.lights = h->d_lights;
-        D.eyes = it.eyes.xyz;
-        D.pairs = pairs ? pairs + 2 * it.out_offset : nullptr;
-        D.weights = weights ? weights + it.out_offset : nullptr;
-        D.counter = d_counters + k;
-        D.capacity = it.out_capacity;
-        D.n_lights = h->n_lights;
-        D.n_nodes = h->n_nodes;
-        D.leaf_size = h->leaf_size;
-        D.n_virtual = h->n_lights ? (uint32_t)nv : 0u;   // no lights: nothing to do
-        D.width = it.eyes.width;
-        D.shift_offset = it.eyes.shift_offset;
-        D.pixel_base = it.eyes.pixel_base;
-        D.n_samples = n_samples;
-        D.psi_s0 = psi_s0;
-        D.s = it.s;
-        for (int q = 0; q < 3; ++q) {
-            D.root_lo[q] = h->box[q];
-            D.root_hi[q] = h->box[3 + q];
-        }
-        D.task_begin = (uint32_t)tasks;
-        S.h_task_begin[k] = (uint32_t)tasks;
-        tasks += (D.n_virtual + epw - 1) / epw;
-        if (tasks > 0xFFFFFFF0ull) return fail(HRR_E_INVALID, "too many tasks in one launch");
-        dmax = std::max(dmax, h->depth);
-    }
-    S.h_task_begin[n] = (uint32_t)tasks;
-
-    // pinned staging: items, task table, then readback words
-    const size_t items_bytes = n * sizeof(ItemDesc);
-    const size_t tb_bytes = (n + 1) * sizeof(uint32_t);
-    const size_t read_words = n + 1 + ST_N;
-    const size_t pin_words = read_words + (items_bytes + tb_bytes + 7) / 8 + 2;
-    if (S.h_pinned_n < pin_words) {
-        if (S.h_pinned) (void)hipHostFree(S.h_pinned);
-        S.h_pinned = nullptr;
-        S.h_pinned_n = 0;
-        if ((e = hipHostMalloc((void**)&S.h_pinned, pin_words * 8, hipHostMallocDefault)) != hipSuccess)
-            return hip_fail(e, "pinned staging");
-        S.h_pinned_n = pin_words;
-    }
-    unsigned char* up = reinterpret_cast<unsigned char*>(S.h_pinned + read_words);
-    memcpy(up, S.h_items.data(), items_bytes);
-    memcpy(up + items_bytes, S.h_task_begin.data(), tb_bytes);
-
-    if ((e = S.items.ensure(items_bytes)) != hipSuccess) return hip_fail(e, "item table");
-    if ((e = S.task_begin.ensure(tb_bytes)) != hipSuccess) return hip_fail(e, "task table");
-    if ((e = hipMemcpyAsync(S.items.p, up, items_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return hip_fail(e, "upload items");
-    if ((e = hipMemcpyAsync(S.task_begin.p, up + items_bytes, tb_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return hip_fail(e, "upload tasks");
-    if ((e = hipMemsetAsync(d_counters, 0, n * sizeof(unsigned long long), stream)) != hipSuccess)
-        return hip_fail(e, "clear counters");
-    if ((e = hipMemsetAsync(d_misc, 0, 16 * sizeof(unsigned long long), stream)) != hipSuccess)
-        return hip_fail(e, "clear misc");
-
-    if (tasks > 0) {
-        const int with_w = weights != nullptr;
-        const size_t lds_wave = hrr_trav_lds_per_wave(cap, with_w);
-        const size_t lds_block = hrr_trav_lds_per_block((uint32_t)n, lds_wave);
-        int bpc = 0;
-        if ((e = hrr_traverse_occupancy(epw, method, stats, with_w, lds_block, &bpc)) != hipSuccess)
-            return hip_fail(e, "occupancy");
-        if (bpc <= 0) return fail(HRR_E_INVALID, "stack of %u entries does not fit in LDS", cap);
-        const uint64_t need_blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
-        const uint32_t blocks = (uint32_t)std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, need_blocks);
-        const uint32_t half = cap / 2;
-        const uint64_t bound = 128ull * (dmax + 2);
-        const uint32_t spill_cap = (uint32_t)(((bound + half - 1) / half) * half + half);
-        const size_t spill_bytes = (size_t)blocks * kWavesPerBlock * spill_cap * sizeof(unsigned long long);
-        if ((e = S.spill.ensure(spill_bytes)) != hipSuccess) return hip_fail(e, "spill stacks");
-
-        TravArgs A;
-        memset(&A, 0, sizeof A);
-        A.items = static_cast<const ItemDesc*>(S.items.p);
-        A.task_begin = static_cast<const uint32_t*>(S.task_begin.p);
-        A.n_items = (uint32_t)n;
-        A.n_tasks = (uint32_t)tasks;
-        A.task_counter = reinterpret_cast<uint32_t*>(d_misc + 0);
-        A.tile = ctx->d_tile;
-        A.spill = static_cast<unsigned long long*>(S.spill.p);
-        A.spill_cap = spill_cap;
-        A.stack_cap = cap;
-        A.lds_per_wave = (uint32_t)lds_wave;
-        A.stats = stats ? d_misc + 2 : nullptr;
-        A.error = reinterpret_cast<uint32_t*>(d_misc + 1);
-        if ((e = hrr_launch_traverse(&A, epw, method, stats, with_w, blocks, stream)) != hipSuccess)
-            return hip_fail(e, "traverse launch");
-    }
-    if ((e = hipMemcpyAsync(S.h_pinned, d_counters, n * sizeof(unsigned long long), hipMemcpyDeviceToHost, stream)) !=
-        hipSuccess)
-        return hip_fail(e, "read counters");
-    if ((e = hipMemcpyAsync(S.h_pinned + n, d_misc + 1, (1 + ST_N) * sizeof(unsigned long long),
-                            hipMemcpyDeviceToHost, stream)) != hipSuccess)
-        return hip_fail(e, "read status");
-    return HRR_OK;
 }
 
 static void fill_stats(const unsigned long long* st, hrr_stats* out) {
@@ -340,7 +205,7 @@ HRR_EXPORT hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint3
                                     uint32_t method, uint32_t* argmin_out, uint32_t* min_out,
                                     unsigned long long* n_invalid_dev, void* stream) {
     if (!ctx) return fail(HRR_E_INVALID, "hrr_range_min: null context");
-    if (method > 1) return fail(HRR_E_INVALID, "hrr_range_min: unknown method %u", method);
+    if (method > 2) return fail(HRR_E_INVALID, "hrr_range_min: unknown method %u", method);
     if (n == 0) return HRR_OK;
     if (!a || !b || !r || !argmin_out || !min_out) return fail(HRR_E_INVALID, "hrr_range_min: null array");
     hipError_t e = hipSetDevice(ctx->device);
@@ -461,21 +326,25 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
     hrr_status st = launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, pairs, weights, stream);
     if (st != HRR_OK) return st;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "traverse");
+    if ((st = finish_items(ctx, S, pairs, weights, stream)) != HRR_OK) return st;
     const size_t n = items.size();
     bool overflow = false;
     uint64_t total = 0;
     for (size_t k = 0; k < n; ++k) {
-        counts[k] = S.h_pinned[k];
+        counts[k] = S.counts[k];
         total += counts[k];
         if (counts[k] > items[k].out_capacity) overflow = true;
     }
-    const uint32_t err = (uint32_t)S.h_pinned[pinned_error_index(n)];
     if (stats) {
         memset(stats, 0, sizeof *stats);
-        if (want_stats) fill_stats(S.h_pinned + pinned_stats_index(n), stats);
+        if (want_stats) fill_stats(S.stat, stats);
         stats->pairs = total;
     }
-    if (err) return fail(HRR_E_DEVICE, "traversal kernel reported error %u (stack spill region exhausted)", err);
+    if (S.error & ERR_SPILL_OVERFLOW)
+        return fail(HRR_E_DEVICE, "traversal kernel exhausted its stack spill region");
+    if (S.error & ERR_PARTIALS_OVERFLOW)
+        return fail(HRR_E_DEVICE, "traversal kernel exhausted its partial-chunk list");
+    if (S.error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", S.error);
     if (overflow) return fail(HRR_E_OVERFLOW, "output capacity exceeded");
     return HRR_OK;
 }

@@ -55,14 +55,32 @@ struct HostItem {
     uint64_t out_offset, out_capacity;
 };
 
+// Host copy of what finish_items needs per item of a launch.
+struct ItemMeta {
+    unsigned long long out_offset, capacity, slack, slack_off, partial_off;
+    uint32_t partial_cap, chunk_shift;
+};
+
 // Per-launch device scratch: one set per stream slot so that concurrent
 // launches (the server) never share queue heads or counters.
 struct LaunchScratch {
-    DevBuf items, task_begin, counters, misc, spill;
+    DevBuf items, task_begin, counters, misc, spill, partials, slack_pairs, slack_weights, segments;
     std::vector<ItemDesc> h_items;
     std::vector<uint32_t> h_task_begin;
-    unsigned long long* h_pinned = nullptr;   // pinned readback area
+    std::vector<unsigned long long> h_partial_off;   // per item, first entry in `partials`
+    unsigned long long* h_pinned = nullptr;          // pinned staging / readback area
     size_t h_pinned_n = 0;
+    std::vector<unsigned long long> h_partials;       // host copy for hole filling
+    std::vector<unsigned long long> h_segments;
+    std::vector<ItemMeta> meta;
+    size_t n_items = 0;
+    bool with_weights = false;
+    bool stats = false;
+    // results of finish_items
+    std::vector<unsigned long long> counts;    // true pairs per item
+    std::vector<unsigned long long> stored;    // valid pairs stored at the front of each slice
+    uint32_t error = 0;
+    unsigned long long stat[ST_N] = {0};
 };
 
 struct Server;
@@ -94,17 +112,15 @@ int ilog2_floor(uint64_t x);
 void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes,
                    uint32_t* epw, uint32_t* cap);
 
-// Run a set of items in one persistent launch on `stream` with scratch `S`.
-// When `sync` is false the call only enqueues work and the caller reads the
-// counters later from S.h_pinned (n_items counters, then error word, then
-// stats) after synchronising the stream.
+// Enqueue one persistent launch of a set of items on `stream` with scratch
+// `S`, and the readback of its counters.  After the stream has been
+// synchronised, finish_items() moves pairs into the holes left by partly
+// filled output chunks (a second small launch, synchronised inside) and fills
+// S.counts / S.stored / S.error / S.stat.
 hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
                         uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
                         uint32_t* pairs, float* weights, hipStream_t stream);
-
-// Readback layout in S.h_pinned after a launch.
-inline size_t pinned_error_index(size_t n_items) { return n_items; }
-inline size_t pinned_stats_index(size_t n_items) { return n_items + 1; }
+hrr_status finish_items(hrr_ctx* ctx, LaunchScratch& S, uint32_t* pairs, float* weights, hipStream_t stream);
 
 void release_scratch(LaunchScratch& S);
 

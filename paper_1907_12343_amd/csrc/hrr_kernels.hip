@@ -15,8 +15,9 @@
 // -- the child that contains the parent's argmin inherits it, the other needs
 // one range-minimum query -- bounds both children, and the survivors are
 // pushed back with ballot/mbcnt compaction.  Leaves with one light are tested
-// exactly at the parent; accepted pairs are staged in LDS and flushed with one
-// 64-bit atomic per chunk.  The stack spills in halves to a per-wave region
+// exactly at the parent; accepted pairs go straight from the lanes into an
+// output chunk the wave owns (one atomic per chunk of thousands of pairs, see
+// emit_put).  The stack spills in halves to a per-wave region
 // of device memory when it would overflow LDS; its size is bounded by
 // 128 entries per tree level (see stack_spill).
 //
@@ -165,6 +166,7 @@ __global__ __launch_bounds__(256) void rmq_kernel(const uint32_t* __restrict__ A
     }
 }
 
+
 // ---------------------------------------------------------------------------
 // traversal kernel
 // ---------------------------------------------------------------------------
@@ -176,11 +178,9 @@ struct EyeState {
     uint32_t u;     // virtual eye index emitted as the pair's first component
 };
 
-// LDS of one wave: stack ring, staged pairs, staged weights, eye table.
+// LDS of one wave: stack ring and eye table.
 struct WaveLds {
     uint2* stack;
-    uint2* stage;
-    float* wstage;
     uint32_t* eyes;   // 8 words per slot
 };
 
@@ -236,36 +236,91 @@ __device__ __forceinline__ void stack_refill(StackState& st, const WaveLds& L, c
     ++st.spills;
 }
 
-// ---- staged output ----
+// ---- pair output in per-wave chunks ----
+//
+// An item's output positions are cut into chunks of 2^chunk_shift pairs.  A
+// wave takes a whole chunk from the item's chunk counter (one device-scope
+// atomic per chunk instead of one per flush: a single address serialises
+// those atomics) and writes its accepted pairs into it directly from the
+// lanes, compacted with ballot/mbcnt.  Every wave leaves at most one partly
+// filled chunk per item; it records (chunk, fill) so that the host can move
+// the pairs found past the final count into those holes.  Positions at or
+// past the caller's capacity go to a library slack area, positions past that
+// are dropped (the count stays exact).
+constexpr unsigned long long kNoChunk = ~0ull;
 
-__device__ __forceinline__ void stage_flush(uint32_t& staged, const WaveLds& L, const ItemDesc& D,
-                                            bool with_w) {
-    if (staged == 0) return;
-    wave_sync();
-    unsigned long long base = 0;
-    if (lane_id() == 0) base = atomicAdd(D.counter, (unsigned long long)staged);
-    base = ((unsigned long long)uni((uint32_t)(base >> 32)) << 32) | uni((uint32_t)base);
-    for (uint32_t t = lane_id(); t < staged; t += kWave) {
-        const unsigned long long pos = base + t;
-        if (pos < D.capacity) {
-            reinterpret_cast<uint2*>(D.pairs)[pos] = L.stage[t];
-            if (with_w) D.weights[pos] = L.wstage[t];
-        }
-    }
-    wave_sync();
-    staged = 0;
+struct OutState {
+    unsigned long long chunk;
+    unsigned long long count;
+    uint32_t fill;
+};
+
+__device__ __forceinline__ unsigned long long uni64(unsigned long long x) {
+    return ((unsigned long long)uni((uint32_t)(x >> 32)) << 32) | uni((uint32_t)x);
 }
 
-// Stage up to one pair per lane; the caller guarantees room for 64.
-__device__ __forceinline__ void stage_put(uint32_t& staged, const WaveLds& L, bool emit, uint32_t u,
-                                          uint32_t i, float w, bool with_w) {
-    const uint64_t m = ballot(emit);
-    if (emit) {
-        const uint32_t at = staged + count_below(m);
-        L.stage[at] = make_uint2(u, i);
-        if (with_w) L.wstage[at] = w;
+__device__ __forceinline__ unsigned long long alloc_chunk(const ItemDesc& D) {
+    unsigned long long c = 0;
+    if (lane_id() == 0) c = atomicAdd(D.counters + CNT_CHUNKS, 1ull);
+    return uni64(c);
+}
+
+template <bool W>
+__device__ __forceinline__ void store_pair(const ItemDesc& D, unsigned long long p, uint2 pr, float w) {
+    if (p < D.capacity) {
+        reinterpret_cast<uint2*>(D.pairs)[p] = pr;
+        if (W) D.weights[p] = w;
+    } else if (p - D.capacity < D.slack) {
+        const unsigned long long q = p - D.capacity;
+        reinterpret_cast<uint2*>(D.slack_pairs)[q] = pr;
+        if (W) D.slack_weights[q] = w;
     }
-    staged += (uint32_t)__popcll(m);
+}
+
+// Emit at most one pair per lane (uniform control flow).
+template <bool W>
+__device__ __forceinline__ void emit_put(OutState& O, const ItemDesc& D, bool emit, uint32_t u, uint32_t i, float w) {
+    const uint64_t m = ballot(emit);
+    const uint32_t cnt = (uint32_t)__popcll(m);
+    if (cnt == 0) return;
+    const uint32_t shift = D.chunk_shift;
+    const uint32_t C = 1u << shift;
+    if (O.chunk == kNoChunk) {
+        O.chunk = alloc_chunk(D);
+        O.fill = 0;
+    }
+    unsigned long long next = kNoChunk;
+    if (O.fill + cnt > C) next = alloc_chunk(D);
+    if (emit) {
+        const uint32_t pos = O.fill + count_below(m);
+        const unsigned long long p = pos < C ? (O.chunk << shift) + pos : (next << shift) + (pos - C);
+        store_pair<W>(D, p, make_uint2(u, i), w);
+    }
+    O.count += cnt;
+    O.fill += cnt;
+    if (O.fill >= C) {
+        O.chunk = next;
+        O.fill -= C;
+    }
+}
+
+// A wave leaves an item: publish its count and its partly filled chunk.
+__device__ __forceinline__ void close_item(OutState& O, const ItemDesc& D, uint32_t* err) {
+    if (lane_id() == 0) {
+        if (O.chunk != kNoChunk && O.fill > 0) {
+            const unsigned long long at = atomicAdd(D.counters + CNT_PARTIALS, 1ull);
+            if (at < D.partial_cap) {
+                D.partials[2 * at] = O.chunk;
+                D.partials[2 * at + 1] = O.fill;
+            } else {
+                atomicOr(err, (uint32_t)ERR_PARTIALS_OVERFLOW);
+            }
+        }
+        if (O.count) atomicAdd(D.counters + CNT_PAIRS, O.count);
+    }
+    O.chunk = kNoChunk;
+    O.fill = 0;
+    O.count = 0;
 }
 
 __device__ __forceinline__ EyeState load_eye(const ItemDesc& D, const uint32_t* tile, uint32_t u) {
@@ -291,12 +346,10 @@ __device__ __forceinline__ EyeState load_eye(const ItemDesc& D, const uint32_t* 
 // and hold more than one light.  Lane-local loops; emissions are compacted
 // every step.
 template <bool W>
-__device__ __forceinline__ void leaf_lights(uint32_t& staged, const WaveLds& L, const ItemDesc& D,
-                                            const EyeState& E, uint32_t la, uint32_t ln, uint32_t ra,
-                                            uint32_t rn, uint64_t& tests) {
+__device__ __forceinline__ void leaf_lights(OutState& O, const ItemDesc& D, const EyeState& E, uint32_t la,
+                                            uint32_t ln, uint32_t ra, uint32_t rn, uint64_t& tests) {
     const uint32_t total = ln + rn;
     for (uint32_t q = 0; ballot(q < total); ++q) {
-        if (staged + kWave > kStage) stage_flush(staged, L, D, W);
         const bool act = q < total;
         bool emit = false;
         uint32_t i = 0;
@@ -310,7 +363,7 @@ __device__ __forceinline__ void leaf_lights(uint32_t& staged, const WaveLds& L, 
             if (W) w = 1.0f / p;
             ++tests;
         }
-        stage_put(staged, L, emit, E.u, i, w, W);
+        emit_put<W>(O, D, emit, E.u, i, w);
     }
 }
 
@@ -331,10 +384,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
     unsigned char* base = wave_area + (size_t)wv * A.lds_per_wave;
     WaveLds L;
     L.stack = reinterpret_cast<uint2*>(base);
-    L.stage = reinterpret_cast<uint2*>(base + (size_t)cap * sizeof(uint2));
-    L.wstage = reinterpret_cast<float*>(base + (size_t)cap * sizeof(uint2) + kStage * sizeof(uint2));
-    L.eyes = reinterpret_cast<uint32_t*>(base + (size_t)cap * sizeof(uint2) + kStage * sizeof(uint2) +
-                                         (W ? kStage * sizeof(float) : 0));
+    L.eyes = reinterpret_cast<uint32_t*>(base + (size_t)cap * sizeof(uint2));
     uint2* spill = reinterpret_cast<uint2*>(A.spill) + (size_t)wave_gid * A.spill_cap;
 
     uint64_t st_eyes = 0, st_visits = 0, st_rmq = 0, st_leaf = 0, st_spills = 0;
@@ -342,7 +392,10 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
 
     uint32_t cur = 0xFFFFFFFFu;
     ItemDesc D;
-    uint32_t staged = 0;
+    OutState O;
+    O.chunk = kNoChunk;
+    O.fill = 0;
+    O.count = 0;
 
     for (;;) {
         uint32_t t = 0;
@@ -358,7 +411,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
         }
         const uint32_t it = uni(lo);
         if (it != cur) {
-            if (cur != 0xFFFFFFFFu) stage_flush(staged, L, D, W);
+            if (cur != 0xFFFFFFFFu) close_item(O, D, A.error);
             cur = it;
             D = A.items[it];
         }
@@ -400,10 +453,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
             if (D.n_nodes == 0) {
                 // the whole light set is one leaf: exact tests of its <= 8 lights
                 uint64_t tests = 0;
-                const uint32_t n_here = act ? N : 0u;
                 if (EPW == 1) {
                     // spread the lights of the single eye over the lanes
-                    if (staged + kWave > kStage) stage_flush(staged, L, D, W);
                     const bool a1 = lane < N;
                     bool emit = false;
                     float w = 0.0f;
@@ -415,9 +466,9 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
                         if (W) w = 1.0f / p;
                         ++tests;
                     }
-                    stage_put(staged, L, emit, E.u, lane, w, W);
+                    emit_put<W>(O, D, emit, E.u, lane, w);
                 } else {
-                    leaf_lights<W>(staged, L, D, E, 0u, n_here, 0u, 0u, tests);
+                    leaf_lights<W>(O, D, E, 0u, act ? N : 0u, 0u, 0u, tests);
                 }
                 if (STATS) st_leaf += tests;
                 continue;
@@ -520,14 +571,13 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
             }
 
             // one-light leaves accepted at the parent
-            if (staged + 2u * kWave > kStage) stage_flush(staged, L, D, W);
-            stage_put(staged, L, emitL, E.u, a, wL, W);
-            stage_put(staged, L, emitR, E.u, c, wR, W);
+            emit_put<W>(O, D, emitL, E.u, a, wL);
+            emit_put<W>(O, D, emitR, E.u, c, wR);
 
             // multi-light leaves
             if (ballot(mlN + mrN > 0u)) {
                 uint64_t tests = 0;
-                leaf_lights<W>(staged, L, D, E, mlA, mlN, mrA, mrN, tests);
+                leaf_lights<W>(O, D, E, mlA, mlN, mrA, mrN, tests);
                 if (STATS) st_leaf += tests;
             }
         }
@@ -536,7 +586,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
             st_maxstack = max(st_maxstack, S.max_total);
         }
     }
-    if (cur != 0xFFFFFFFFu) stage_flush(staged, L, D, W);
+    if (cur != 0xFFFFFFFFu) close_item(O, D, A.error);
 
     if (STATS && A.stats) {
         uint64_t v[6] = {st_eyes, 0, st_visits, st_rmq, st_leaf, st_spills};
@@ -548,13 +598,36 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
         uint32_t mx = st_maxstack;
         for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor(mx, o));
         if (lane == 0) {
-            // eyes / spills / max stack are per-wave quantities kept in every lane
+            // eyes / visits / spills / max stack are per-wave quantities kept in every lane
             atomicAdd(A.stats + ST_EYES, (unsigned long long)(v[0] / kWave));
             atomicAdd(A.stats + ST_VISITS, (unsigned long long)(v[2] / kWave));
             atomicAdd(A.stats + ST_RMQ, (unsigned long long)v[3]);
             atomicAdd(A.stats + ST_LEAF, (unsigned long long)v[4]);
             atomicAdd(A.stats + ST_SPILLS, (unsigned long long)(v[5] / kWave));
             atomicMax(A.stats + ST_MAXSTACK, (unsigned long long)mx);
+        }
+    }
+}
+
+// Hole filling after a traversal: segment q copies len[q] pairs (and weights)
+// from position src[q] (the caller's buffer, or the slack area when bit 63 is
+// set) to position dst[q] of the caller's buffer.  Sources and destinations
+// never overlap: sources lie at or past an item's final pair count,
+// destinations below it.
+__global__ __launch_bounds__(256) void move_pairs_kernel(const unsigned long long* __restrict__ seg, uint32_t n_seg,
+                                                         uint32_t* pairs, float* weights, const uint32_t* slack_pairs,
+                                                         const float* slack_weights) {
+    constexpr unsigned long long kSlack = 1ull << 63;
+    for (uint32_t q = blockIdx.x; q < n_seg; q += gridDim.x) {
+        const unsigned long long src = seg[3 * q], dst = seg[3 * q + 1], len = seg[3 * q + 2];
+        const bool from_slack = (src & kSlack) != 0;
+        const unsigned long long s0 = src & ~kSlack;
+        const uint2* sp = reinterpret_cast<const uint2*>(from_slack ? slack_pairs : pairs) + s0;
+        const float* sw = weights ? (from_slack ? slack_weights : weights) + s0 : nullptr;
+        uint2* dp = reinterpret_cast<uint2*>(pairs) + dst;
+        for (unsigned long long t = threadIdx.x; t < len; t += blockDim.x) {
+            dp[t] = sp[t];
+            if (weights) weights[dst + t] = sw[t];
         }
     }
 }
@@ -577,8 +650,20 @@ extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const
     if (blocks < 1) blocks = 1;
     if (method == 1)
         hipLaunchKernelGGL(hrr::rmq_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
+    else if (method == 2)
+        hipLaunchKernelGGL(hrr::rmq_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     else
         hipLaunchKernelGGL(hrr::rmq_kernel<0>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
+    return hipGetLastError();
+}
+
+extern "C" hipError_t hrr_launch_move_pairs(const unsigned long long* seg, uint32_t n_seg, uint32_t* pairs,
+                                            float* weights, const uint32_t* slack_pairs, const float* slack_weights,
+                                            hipStream_t stream) {
+    if (n_seg == 0) return hipSuccess;
+    const uint32_t blocks = n_seg < 4096u ? n_seg : 4096u;
+    hipLaunchKernelGGL(hrr::move_pairs_kernel, dim3(blocks), dim3(256), 0, stream, seg, n_seg, pairs, weights,
+                       slack_pairs, slack_weights);
     return hipGetLastError();
 }
 
@@ -609,15 +694,16 @@ hipError_t pick_stats(const hrr::TravArgs& A, bool st, bool w, uint32_t blocks, 
 template <int EPW>
 hipError_t pick_method(const hrr::TravArgs& A, uint32_t method, bool st, bool w, uint32_t blocks, size_t lds,
                        hipStream_t s) {
-    return method == 1 ? pick_stats<EPW, 1>(A, st, w, blocks, lds, s) : pick_stats<EPW, 0>(A, st, w, blocks, lds, s);
+    if (method == 1) return pick_stats<EPW, 1>(A, st, w, blocks, lds, s);
+    if (method == 2) return pick_stats<EPW, 2>(A, st, w, blocks, lds, s);
+    return pick_stats<EPW, 0>(A, st, w, blocks, lds, s);
 }
 
 }  // namespace
 
 // LDS bytes of one wave for a given stack size.
-extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap, int with_weights) {
-    return (size_t)stack_cap * sizeof(uint2) + hrr::kStage * sizeof(uint2) +
-           (with_weights ? hrr::kStage * sizeof(float) : 0) + 8 * 8 * sizeof(uint32_t);
+extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap) {
+    return (size_t)stack_cap * sizeof(uint2) + 8 * 8 * sizeof(uint32_t);
 }
 
 // Dynamic LDS bytes of one block.
@@ -645,7 +731,7 @@ extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t me
     if (eyes_per_wave == E && method == M && (stats != 0) == S && (with_weights != 0) == W) \
         f = (const void*)hrr::traverse_kernel<E, M, S, W>;
 #define HRR_PICK_SW(E, M) HRR_PICK(E, M, false, false) HRR_PICK(E, M, false, true) HRR_PICK(E, M, true, false) HRR_PICK(E, M, true, true)
-#define HRR_PICK_M(E) HRR_PICK_SW(E, 0) HRR_PICK_SW(E, 1)
+#define HRR_PICK_M(E) HRR_PICK_SW(E, 0) HRR_PICK_SW(E, 1) HRR_PICK_SW(E, 2)
     HRR_PICK_M(1) HRR_PICK_M(2) HRR_PICK_M(4) HRR_PICK_M(8)
 #undef HRR_PICK_M
 #undef HRR_PICK_SW

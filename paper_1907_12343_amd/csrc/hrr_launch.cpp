@@ -1,0 +1,307 @@
+// hrr_launch.cpp -- host side of one persistent traversal launch: work
+// queue and item table set-up, output chunk sizing, and the hole filling that
+// makes each item's pairs dense after the kernel.
+#include <hip/hip_runtime_api.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "hrr_ctx.hpp"
+
+extern "C" hipError_t hrr_launch_traverse(const hrr::TravArgs* A, uint32_t eyes_per_wave, uint32_t method,
+                                          int stats, int with_weights, uint32_t blocks, hipStream_t stream);
+extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap);
+extern "C" size_t hrr_trav_lds_per_block(uint32_t n_items, size_t lds_per_wave);
+extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t method, int stats, int with_weights,
+                                             size_t lds_per_block, int* blocks_per_cu);
+extern "C" hipError_t hrr_launch_move_pairs(const unsigned long long* seg, uint32_t n_seg, uint32_t* pairs,
+                                            float* weights, const uint32_t* slack_pairs, const float* slack_weights,
+                                            hipStream_t stream);
+
+namespace hrr {
+
+namespace {
+
+bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
+
+constexpr unsigned long long kSlackFlag = 1ull << 63;
+
+}  // namespace
+
+hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
+                        uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
+                        uint32_t* pairs, float* weights, hipStream_t stream) {
+    const size_t n = items.size();
+    if (n == 0 || n > kMaxItemsPerLaunch)
+        return fail(HRR_E_INVALID, "items per launch must be in [1, %u]", kMaxItemsPerLaunch);
+    if (!(epw == 1 || epw == 2 || epw == 4 || epw == 8))
+        return fail(HRR_E_INVALID, "eyes_per_wave must be 1, 2, 4 or 8");
+    if (!is_pow2(cap) || cap < 256 || cap > 4096)
+        return fail(HRR_E_INVALID, "stack_entries must be a power of two in [256, 4096]");
+    if (method > 2) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
+    if (n_samples == 0) n_samples = 1;
+    const int with_w = weights != nullptr;
+
+    // ---- grid: persistent waves, as many as stay resident ----
+    const size_t lds_wave = hrr_trav_lds_per_wave(cap);
+    const size_t lds_block = hrr_trav_lds_per_block((uint32_t)n, lds_wave);
+    int bpc = 0;
+    hipError_t e;
+    if ((e = hrr_traverse_occupancy(epw, method, stats, with_w, lds_block, &bpc)) != hipSuccess)
+        return hip_fail(e, "occupancy");
+    if (bpc <= 0) return fail(HRR_E_INVALID, "stack of %u entries does not fit in LDS", cap);
+
+    std::vector<uint64_t> tasks_of(n);
+    uint64_t tasks = 0;
+    uint32_t dmax = 0;
+    for (size_t k = 0; k < n; ++k) {
+        const HostItem& it = items[k];
+        const hrr_hierarchy* h = it.h;
+        if (!h) return fail(HRR_E_INVALID, "item %zu: null hierarchy", k);
+        if (h->owner != ctx) return fail(HRR_E_INVALID, "item %zu: hierarchy belongs to another context", k);
+        if (!(it.s > 0.0f) || !isfinite(it.s)) return fail(HRR_E_INVALID, "item %zu: s must be finite and > 0", k);
+        if (it.eyes.n > 0 && !it.eyes.xyz) return fail(HRR_E_INVALID, "item %zu: null eye positions", k);
+        if (it.eyes.width == 0) return fail(HRR_E_INVALID, "item %zu: width must be >= 1", k);
+        if (it.out_capacity > 0 && !pairs) return fail(HRR_E_INVALID, "item %zu: null pairs buffer", k);
+        const uint64_t nv = (uint64_t)it.eyes.n * n_samples;
+        if (nv > 0xFFFFFFFFull) return fail(HRR_E_INVALID, "item %zu: eyes x samples exceeds 2^32 - 1", k);
+        tasks_of[k] = h->n_lights ? (nv + epw - 1) / epw : 0;
+        tasks += tasks_of[k];
+        if (tasks > 0xFFFFFFF0ull) return fail(HRR_E_INVALID, "too many tasks in one launch");
+        dmax = std::max(dmax, h->depth);
+    }
+    const uint64_t need_blocks = (tasks + kWavesPerBlock - 1) / kWavesPerBlock;
+    const uint32_t blocks = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)ctx->n_cu * bpc, need_blocks));
+    const uint64_t waves = (uint64_t)blocks * kWavesPerBlock;
+
+    // ---- per-item output chunks, slack and partial lists ----
+    std::vector<ItemMeta>& M = S.meta;
+    M.assign(n, ItemMeta{});
+    unsigned long long slack_total = 0, partial_total = 0;
+    for (size_t k = 0; k < n; ++k) {
+        const uint64_t wk = std::max<uint64_t>(1, std::min<uint64_t>(waves, tasks_of[k]));
+        const unsigned long long capk = items[k].out_capacity;
+        // about four chunks per touching wave, 64..8192 pairs
+        uint32_t shift = kMinChunkShift;
+        while (shift < kMaxChunkShift && (capk >> (shift + 1)) >= 4 * wk) ++shift;
+        ItemMeta& m = M[k];
+        m.out_offset = items[k].out_offset;
+        m.capacity = capk;
+        m.chunk_shift = shift;
+        m.slack = capk ? 2ull * wk << shift : 0ull;
+        m.slack_off = slack_total;
+        slack_total += m.slack;
+        m.partial_cap = (uint32_t)wk;
+        m.partial_off = partial_total;
+        partial_total += wk;
+    }
+
+    S.n_items = n;
+    S.with_weights = with_w;
+    S.stats = stats;
+    if ((e = S.counters.ensure(n * CNT_STRIDE * sizeof(unsigned long long))) != hipSuccess) return hip_fail(e, "counters");
+    if ((e = S.misc.ensure(16 * sizeof(unsigned long long))) != hipSuccess) return hip_fail(e, "misc");
+    if ((e = S.partials.ensure(std::max<unsigned long long>(partial_total, 1) * 2 * sizeof(unsigned long long))) != hipSuccess)
+        return hip_fail(e, "partial-chunk list");
+    if ((e = S.slack_pairs.ensure(std::max<unsigned long long>(slack_total, 1) * 2 * sizeof(uint32_t))) != hipSuccess)
+        return hip_fail(e, "output slack");
+    if (with_w && (e = S.slack_weights.ensure(std::max<unsigned long long>(slack_total, 1) * sizeof(float))) != hipSuccess)
+        return hip_fail(e, "weight slack");
+    unsigned long long* d_counters = static_cast<unsigned long long*>(S.counters.p);
+    unsigned long long* d_misc = static_cast<unsigned long long*>(S.misc.p);
+    unsigned long long* d_partials = static_cast<unsigned long long*>(S.partials.p);
+
+    S.h_items.assign(n, ItemDesc{});
+    S.h_task_begin.assign(n + 1, 0);
+    uint64_t tb = 0;
+    for (size_t k = 0; k < n; ++k) {
+        const HostItem& it = items[k];
+        const hrr_hierarchy* h = it.h;
+        const ItemMeta& m = M[k];
+        ItemDesc& D = S.h_items[k];
+        D.nodes = h->d_nodes;
+        D.lights = h->d_lights;
+        D.eyes = it.eyes.xyz;
+        D.pairs = pairs ? pairs + 2 * it.out_offset : nullptr;
+        D.weights = weights ? weights + it.out_offset : nullptr;
+        D.slack_pairs = static_cast<uint32_t*>(S.slack_pairs.p) + 2 * m.slack_off;
+        D.slack_weights = with_w ? static_cast<float*>(S.slack_weights.p) + m.slack_off : nullptr;
+        D.counters = d_counters + k * CNT_STRIDE;
+        D.partials = d_partials + 2 * m.partial_off;
+        D.capacity = it.out_capacity;
+        D.slack = m.slack;
+        D.partial_cap = m.partial_cap;
+        D.chunk_shift = m.chunk_shift;
+        D.n_lights = h->n_lights;
+        D.n_nodes = h->n_nodes;
+        D.leaf_size = h->leaf_size;
+        D.n_virtual = h->n_lights ? (uint32_t)((uint64_t)it.eyes.n * n_samples) : 0u;
+        D.width = it.eyes.width;
+        D.shift_offset = it.eyes.shift_offset;
+        D.pixel_base = it.eyes.pixel_base;
+        D.n_samples = n_samples;
+        D.psi_s0 = psi_s0;
+        D.s = it.s;
+        for (int q = 0; q < 3; ++q) {
+            D.root_lo[q] = h->box[q];
+            D.root_hi[q] = h->box[3 + q];
+        }
+        D.task_begin = (uint32_t)tb;
+        S.h_task_begin[k] = (uint32_t)tb;
+        tb += tasks_of[k];
+    }
+    S.h_task_begin[n] = (uint32_t)tasks;
+
+    // pinned staging: readback words first, then the upload of the tables
+    const size_t items_bytes = n * sizeof(ItemDesc);
+    const size_t tb_bytes = (n + 1) * sizeof(uint32_t);
+    const size_t read_words = n * CNT_STRIDE + 1 + ST_N;
+    const size_t pin_words = read_words + (items_bytes + tb_bytes + 7) / 8 + 2;
+    if (S.h_pinned_n < pin_words) {
+        if (S.h_pinned) (void)hipHostFree(S.h_pinned);
+        S.h_pinned = nullptr;
+        S.h_pinned_n = 0;
+        if ((e = hipHostMalloc((void**)&S.h_pinned, pin_words * 8, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "pinned staging");
+        S.h_pinned_n = pin_words;
+    }
+    unsigned char* up = reinterpret_cast<unsigned char*>(S.h_pinned + read_words);
+    memcpy(up, S.h_items.data(), items_bytes);
+    memcpy(up + items_bytes, S.h_task_begin.data(), tb_bytes);
+
+    if ((e = S.items.ensure(items_bytes)) != hipSuccess) return hip_fail(e, "item table");
+    if ((e = S.task_begin.ensure(tb_bytes)) != hipSuccess) return hip_fail(e, "task table");
+    if ((e = hipMemcpyAsync(S.items.p, up, items_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "upload items");
+    if ((e = hipMemcpyAsync(S.task_begin.p, up + items_bytes, tb_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "upload tasks");
+    if ((e = hipMemsetAsync(d_counters, 0, n * CNT_STRIDE * sizeof(unsigned long long), stream)) != hipSuccess)
+        return hip_fail(e, "clear counters");
+    if ((e = hipMemsetAsync(d_misc, 0, 16 * sizeof(unsigned long long), stream)) != hipSuccess)
+        return hip_fail(e, "clear misc");
+
+    if (tasks > 0) {
+        const uint32_t half = cap / 2;
+        const uint64_t bound = 128ull * (dmax + 2);
+        const uint32_t spill_cap = (uint32_t)(((bound + half - 1) / half) * half + half);
+        const size_t spill_bytes = (size_t)waves * spill_cap * sizeof(unsigned long long);
+        if ((e = S.spill.ensure(spill_bytes)) != hipSuccess) return hip_fail(e, "spill stacks");
+
+        TravArgs A;
+        memset(&A, 0, sizeof A);
+        A.items = static_cast<const ItemDesc*>(S.items.p);
+        A.task_begin = static_cast<const uint32_t*>(S.task_begin.p);
+        A.n_items = (uint32_t)n;
+        A.n_tasks = (uint32_t)tasks;
+        A.task_counter = reinterpret_cast<uint32_t*>(d_misc + 0);
+        A.tile = ctx->d_tile;
+        A.spill = static_cast<unsigned long long*>(S.spill.p);
+        A.spill_cap = spill_cap;
+        A.stack_cap = cap;
+        A.lds_per_wave = (uint32_t)lds_wave;
+        A.stats = stats ? d_misc + 2 : nullptr;
+        A.error = reinterpret_cast<uint32_t*>(d_misc + 1);
+        if ((e = hrr_launch_traverse(&A, epw, method, stats, with_w, blocks, stream)) != hipSuccess)
+            return hip_fail(e, "traverse launch");
+    }
+    if ((e = hipMemcpyAsync(S.h_pinned, d_counters, n * CNT_STRIDE * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            stream)) != hipSuccess)
+        return hip_fail(e, "read counters");
+    if ((e = hipMemcpyAsync(S.h_pinned + n * CNT_STRIDE, d_misc + 1, (1 + ST_N) * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, stream)) != hipSuccess)
+        return hip_fail(e, "read status");
+    return HRR_OK;
+}
+
+hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weights, hipStream_t stream) {
+    const size_t n = S.n_items;
+    const std::vector<ItemMeta>& M = S.meta;
+    S.counts.assign(n, 0);
+    S.stored.assign(n, 0);
+    const unsigned long long* rd = S.h_pinned;
+    S.error = (uint32_t)rd[n * CNT_STRIDE];
+    for (int q = 0; q < ST_N; ++q) S.stat[q] = rd[n * CNT_STRIDE + 1 + q];
+    if (S.error) return HRR_OK;   // caller reports
+
+    hipError_t e;
+    S.h_segments.clear();
+    for (size_t k = 0; k < n; ++k) {
+        const unsigned long long cnt = rd[k * CNT_STRIDE + CNT_PAIRS];
+        const unsigned long long K = rd[k * CNT_STRIDE + CNT_CHUNKS];
+        const unsigned long long P = std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], M[k].partial_cap);
+        S.counts[k] = cnt;
+        const ItemMeta& m = M[k];
+        const unsigned long long cap = m.capacity;
+        const unsigned long long target = std::min(cnt, cap);
+        if (target == 0) continue;
+        const unsigned long long C = 1ull << m.chunk_shift;
+        const unsigned long long limit = cap + m.slack;   // stored positions are below this
+        // partly filled chunks (sorted by chunk)
+        std::vector<std::pair<unsigned long long, unsigned long long>> part(P);
+        if (P) {
+            S.h_partials.resize(2 * P);
+            const unsigned long long* src = static_cast<const unsigned long long*>(S.partials.p) + 2 * m.partial_off;
+            if ((e = hipMemcpy(S.h_partials.data(), src, 2 * P * sizeof(unsigned long long), hipMemcpyDeviceToHost)) !=
+                hipSuccess)
+                return hip_fail(e, "read partial chunks");
+            for (unsigned long long q = 0; q < P; ++q) part[q] = {S.h_partials[2 * q], S.h_partials[2 * q + 1]};
+            std::sort(part.begin(), part.end());
+        }
+        // holes below the target length
+        std::vector<std::pair<unsigned long long, unsigned long long>> holes, data;
+        for (auto& pc : part) {
+            const unsigned long long lo = pc.first * C + pc.second;
+            const unsigned long long hi = std::min((pc.first + 1) * C, target);
+            if (lo < hi) holes.push_back({lo, hi});
+        }
+        // stored pairs at or past the target length
+        size_t pi = 0;
+        for (unsigned long long c = target / C; c < K && c * C < limit; ++c) {
+            while (pi < part.size() && part[pi].first < c) ++pi;
+            const unsigned long long fill = (pi < part.size() && part[pi].first == c) ? part[pi].second : C;
+            const unsigned long long lo = std::max(c * C, target);
+            const unsigned long long hi = std::min(c * C + fill, limit);
+            if (lo < hi) data.push_back({lo, hi});
+        }
+        unsigned long long unfilled = 0;
+        size_t hi_ = 0, di = 0;
+        unsigned long long hpos = holes.empty() ? 0 : holes[0].first;
+        unsigned long long dpos = data.empty() ? 0 : data[0].first;
+        while (hi_ < holes.size()) {
+            if (di >= data.size()) {
+                unfilled += holes[hi_].second - hpos;
+                if (++hi_ < holes.size()) hpos = holes[hi_].first;
+                continue;
+            }
+            const unsigned long long len = std::min(holes[hi_].second - hpos, data[di].second - dpos);
+            const unsigned long long src = dpos < cap ? m.out_offset + dpos : (kSlackFlag | (m.slack_off + dpos - cap));
+            S.h_segments.push_back(src);
+            S.h_segments.push_back(m.out_offset + hpos);
+            S.h_segments.push_back(len);
+            hpos += len;
+            dpos += len;
+            if (hpos == holes[hi_].second && ++hi_ < holes.size()) hpos = holes[hi_].first;
+            if (dpos == data[di].second && ++di < data.size()) dpos = data[di].first;
+        }
+        S.stored[k] = target - unfilled;
+    }
+    const size_t n_seg = S.h_segments.size() / 3;
+    if (n_seg) {
+        if ((e = S.segments.ensure(S.h_segments.size() * sizeof(unsigned long long))) != hipSuccess)
+            return hip_fail(e, "segments");
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "before hole filling");
+        if ((e = hipMemcpy(S.segments.p, S.h_segments.data(), S.h_segments.size() * sizeof(unsigned long long),
+                           hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(e, "upload segments");
+        if ((e = hrr_launch_move_pairs(static_cast<const unsigned long long*>(S.segments.p), (uint32_t)n_seg, pairs,
+                                       weights, static_cast<const uint32_t*>(S.slack_pairs.p),
+                                       static_cast<const float*>(S.slack_weights.p), stream)) != hipSuccess)
+            return hip_fail(e, "hole filling");
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hole filling");
+    }
+    return HRR_OK;
+}
+
+}  // namespace hrr

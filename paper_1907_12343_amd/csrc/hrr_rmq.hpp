@@ -24,7 +24,7 @@
 //       Section 2's "right-to-left" sweep reaches by trying exactly i
 //       trailing zeros for i = 0, 1, ...
 //
-// Two implementations compute the same k:
+// Three implementations compute the same k:
 //   rmq_paper  -- the paper's method: case test, left-to-right sweep with
 //                 refinement, right-to-left sweep.  Written from the paper's
 //                 description with gfx950-friendly changes that keep the
@@ -37,6 +37,8 @@
 //                 case a == 0 with no index above the threshold returns 0, the
 //                 reflected-smallest index overall (the printed sweep stops at
 //                 i = B - 1 and would miss it).
+//   rmq_paper_pruned -- the same sweeps, refining only the one candidate
+//                 whose prefix class meets [a,b) (the default).
 //   rmq_direct -- the same three cases, each resolved in O(1) bit
 //                 arithmetic (an ablation of the sweep, no loops).
 //
@@ -133,6 +135,54 @@ HRR_HD uint32_t rmq_paper(uint32_t a, uint32_t b, uint32_t kr) {
     return a == 0 ? 0u : k;
 }
 
+// Does [a,b) hold an index whose bits below i+1 equal `prefix`
+// (prefix < 2^(i+1))?  The first index at or above a with that residue is
+// a + ((prefix - a) mod 2^(i+1)).
+HRR_HD bool prefix_in_range(uint32_t prefix, int i, uint32_t a, uint32_t b) {
+    return ((prefix - a) & low_mask(i + 1)) < b - a;
+}
+
+// The paper's method with its sweeps pruned by that O(1) membership test:
+// the left-to-right sweep still visits the zero bits of k_r from b_h down to
+// k_p, the right-to-left sweep still tries "exactly i trailing zeros" for
+// i = 0, 1, ..., but only the position whose prefix class meets [a,b) is
+// refined (Algorithm 3 finds its reflected-smallest member), through a single
+// refinement call.  A prefix class that misses the range cannot refine into
+// it, so skipping it never changes the answer; the right-to-left sweep
+// remembers the last position that meets the range and refines it once.
+HRR_HD uint32_t rmq_paper_pruned(uint32_t a, uint32_t b, uint32_t kr) {
+    if (in_range(kr, a, b)) return kr;
+    const int kp = kr ? bottom_bit(kr) : 32;
+    const int bh = top_bit(b);
+    int pos = -1;
+    uint32_t low = 0u;
+    if (kp <= bh) {
+        uint32_t zeros = ~kr & low_mask(bh + 1) & ~low_mask(kp);
+        while (zeros) {
+            const int i = top_bit(zeros);
+            zeros ^= 1u << i;
+            const uint32_t prefix = (kr & low_mask(i)) | (1u << i);
+            if (prefix_in_range(prefix, i, a, b)) {
+                pos = i;
+                low = kr & low_mask(i);
+                break;
+            }
+        }
+    }
+    if (pos < 0) {
+        for (int i = 0; i < 32; ++i) {
+            if (i == kp) {
+                if (pos >= 0) break;     // an index above the threshold exists
+                if (a == 0) return 0u;   // none: 0 is the reflected-smallest index
+            }
+            if (a != 0 && ((a - 1u) | low_mask(i)) >= b - 1u) break;
+            if (prefix_in_range(1u << i, i, a, b)) pos = i;
+        }
+        low = 0u;
+    }
+    return refine(seed_candidate(a, pos, low), pos + 1, a, b);
+}
+
 // Index with the most trailing zeros in [lo, hi] (lo <= hi): below the highest
 // bit where lo and hi differ, hi with that bit kept and the rest cleared --
 // unless lo itself is already zero from that bit down.
@@ -179,10 +229,13 @@ HRR_HD uint32_t rmq_direct(uint32_t a, uint32_t b, uint32_t kr) {
     return most_trailing_zeros(a, b - 1u);
 }
 
+// METHOD 0: the paper's sweeps with pruning (default); 1: O(1) ablation;
+// 2: the paper's sweeps refining every candidate (ablation).
 template <int METHOD>
 HRR_HD uint32_t rmq(uint32_t a, uint32_t b, uint32_t kr) {
     if (METHOD == 1) return rmq_direct(a, b, kr);
-    return rmq_paper(a, b, kr);
+    if (METHOD == 2) return rmq_paper(a, b, kr);
+    return rmq_paper_pruned(a, b, kr);
 }
 
 }  // namespace hrr

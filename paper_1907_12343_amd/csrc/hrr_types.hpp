@@ -35,15 +35,22 @@ struct ItemDesc {
     const float* eyes;            // 3 floats per eye
     uint32_t* pairs;              // item's output slice, 2 u32 per pair
     float* weights;               // item's weight slice or null
-    unsigned long long* counter;  // item's pair counter (device)
+    uint32_t* slack_pairs;        // positions >= capacity land here (library memory)
+    float* slack_weights;
+    unsigned long long* counters; // CNT_PAIRS, CNT_CHUNKS, CNT_PARTIALS (device)
+    unsigned long long* partials; // (chunk, fill) of partly filled chunks
     unsigned long long capacity;  // pairs the slice can hold
+    unsigned long long slack;     // pairs the slack area can hold
+    uint32_t partial_cap, chunk_shift;
     uint32_t n_lights, n_nodes, leaf_size, n_virtual;
     uint32_t width, shift_offset, pixel_base, n_samples;
     uint32_t psi_s0, task_begin;
     float s;
     float root_lo[3], root_hi[3];
-    uint32_t pad[3];
 };
+
+// Per-item device counters, one 128-byte line per item.
+enum CounterIdx { CNT_PAIRS = 0, CNT_CHUNKS = 1, CNT_PARTIALS = 2, CNT_STRIDE = 16 };
 
 // Kernel arguments of the persistent traversal launch.
 struct TravArgs {
@@ -63,13 +70,14 @@ struct TravArgs {
 
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
-constexpr uint32_t kStage = 512;        // staged pairs per wave before a flush
 constexpr uint32_t kMaxItemsPerLaunch = 1024;
+constexpr uint32_t kMinChunkShift = 6;  // a chunk holds >= 64 pairs (one emission step)
+constexpr uint32_t kMaxChunkShift = 13;
 constexpr uint32_t kSlotShift = 28;     // stack entry: node | slot << 28
 constexpr uint32_t kMaxNodes = 1u << kSlotShift;
 
 enum StatIdx { ST_EYES = 0, ST_PAIRS, ST_VISITS, ST_RMQ, ST_LEAF, ST_SPILLS, ST_MAXSTACK, ST_N };
 
-enum ErrCode { ERR_NONE = 0, ERR_SPILL_OVERFLOW = 1 };
+enum ErrCode { ERR_NONE = 0, ERR_SPILL_OVERFLOW = 1, ERR_PARTIALS_OVERFLOW = 2 };
 
 }  // namespace hrr
