@@ -87,10 +87,15 @@ int hrr_version(void);
 /* Range minimum of the rotated radical inverse                               */
 /* ------------------------------------------------------------------------- */
 
-#define HRR_RMQ_PAPER 0u   /* the paper's sweeps (Section 2, Algorithms 2 and 3), refining only the
-                              candidate whose prefix class meets the range (default) */
-#define HRR_RMQ_DIRECT 1u  /* same case analysis, each sweep resolved in O(1) bit arithmetic (ablation) */
-#define HRR_RMQ_PAPER_FULL 2u /* the paper's sweeps refining every candidate in turn (ablation) */
+/* All methods return the same (argmin, min); they differ in how the paper's
+ * steps are scheduled on the VALU. */
+#define HRR_RMQ_PAPER 0u      /* default: the paper's case analysis and sweeps (Section 2, Algorithms 2
+                                 and 3) with all candidate flip positions tested at once in bit
+                                 arithmetic, then Algorithm 3's refinement of the winning prefix */
+#define HRR_RMQ_DIRECT 1u     /* ablation: every step in O(1) bit arithmetic, no refinement walk */
+#define HRR_RMQ_PAPER_FULL 2u /* ablation: the sweeps as loops, refining every candidate in turn */
+#define HRR_RMQ_PAPER_LOOP 3u /* ablation: the sweeps as loops, refining only the candidate whose
+                                 prefix class meets the range */
 
 /* For q < n: k = argmin over i in [a[q], b[q]) of (bit_reverse32(i) + r[q])
  * mod 2^32 and v = that minimum (Section 1, v(a,b); Section 2, the argmin
@@ -158,11 +163,13 @@ typedef struct hrr_eyes {
 } hrr_eyes;
 
 #define HRR_F_STATS 1u      /* count node visits, range minima, leaf tests (slower) */
+#define HRR_F_NO_REORDER 2u /* process eyes in index order instead of grouping them by space
+                               (ablation; the result is the same either way) */
 
 typedef struct hrr_traverse_opts {
     uint32_t eyes_per_wave; /* 0 = autotuned; else 1, 2, 4 or 8 eyes share one wavefront */
     uint32_t stack_entries; /* 0 = autotuned; else LDS stack entries per wave, power of two in [256, 4096] */
-    uint32_t rmq_method;    /* HRR_RMQ_PAPER (default), HRR_RMQ_DIRECT or HRR_RMQ_PAPER_FULL */
+    uint32_t rmq_method;    /* HRR_RMQ_PAPER (default) or one of the HRR_RMQ_* ablations */
     uint32_t n_samples;     /* 0 or 1 = one sample per pair; > 1: Section 3 multi-sample */
     uint32_t psi_s0;        /* start of the golden-ratio lattice psi(n) = s0 + n * alpha mod 1 */
     uint32_t flags;         /* HRR_F_* */

@@ -21,8 +21,9 @@ LIB_PATH = os.path.join(_HERE, "libhrr.so")
 
 HRR_OK, HRR_E_INVALID, HRR_E_NOMEM, HRR_E_OVERFLOW = 0, 1, 2, 3
 HRR_E_DEVICE, HRR_E_NOTREADY, HRR_E_CANCELLED, HRR_E_BUSY = 4, 5, 6, 7
-RMQ_PAPER, RMQ_DIRECT, RMQ_PAPER_FULL = 0, 1, 2
+RMQ_PAPER, RMQ_DIRECT, RMQ_PAPER_FULL, RMQ_PAPER_LOOP = 0, 1, 2, 3
 F_STATS = 1
+F_NO_REORDER = 2
 
 _u32, _u64, _i32, _f32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_float
 _P = ctypes.c_void_p
@@ -218,9 +219,10 @@ class Hierarchy:
 
 
 def _opts(eyes_per_wave=0, stack_entries=0, rmq_method=RMQ_PAPER, n_samples=1, psi_s0=0,
-          stats=False):
+          stats=False, reorder=True):
+    flags = (F_STATS if stats else 0) | (0 if reorder else F_NO_REORDER)
     return HrrTraverseOpts(eyes_per_wave, stack_entries, rmq_method, n_samples,
-                           psi_s0 & 0xFFFFFFFF, F_STATS if stats else 0)
+                           psi_s0 & 0xFFFFFFFF, flags)
 
 
 class Context:

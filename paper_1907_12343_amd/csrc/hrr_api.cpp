@@ -85,6 +85,12 @@ void release_scratch(LaunchScratch& S) {
     S.slack_pairs.release();
     S.slack_weights.release();
     S.segments.release();
+    S.order_keys.release();
+    S.order_idx.release();
+    S.order_hist.release();
+    S.order_items.release();
+    S.order_vbegin.release();
+    S.queues.release();
     if (S.h_pinned) (void)hipHostFree(S.h_pinned);
     S.h_pinned = nullptr;
     S.h_pinned_n = 0;
@@ -205,7 +211,7 @@ HRR_EXPORT hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint3
                                     uint32_t method, uint32_t* argmin_out, uint32_t* min_out,
                                     unsigned long long* n_invalid_dev, void* stream) {
     if (!ctx) return fail(HRR_E_INVALID, "hrr_range_min: null context");
-    if (method > 2) return fail(HRR_E_INVALID, "hrr_range_min: unknown method %u", method);
+    if (method > 3) return fail(HRR_E_INVALID, "hrr_range_min: unknown method %u", method);
     if (n == 0) return HRR_OK;
     if (!a || !b || !r || !argmin_out || !min_out) return fail(HRR_E_INVALID, "hrr_range_min: null array");
     hipError_t e = hipSetDevice(ctx->device);
@@ -323,7 +329,8 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
     const uint32_t s0 = opts ? opts->psi_s0 : 0;
     const bool want_stats = opts && (opts->flags & HRR_F_STATS);
     LaunchScratch& S = ctx->scratch;
-    hrr_status st = launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, pairs, weights, stream);
+    const bool reorder = !(opts && (opts->flags & HRR_F_NO_REORDER));
+    hrr_status st = launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, reorder, pairs, weights, stream);
     if (st != HRR_OK) return st;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "traverse");
     if ((st = finish_items(ctx, S, pairs, weights, stream)) != HRR_OK) return st;

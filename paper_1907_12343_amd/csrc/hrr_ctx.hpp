@@ -65,6 +65,7 @@ struct ItemMeta {
 // launches (the server) never share queue heads or counters.
 struct LaunchScratch {
     DevBuf items, task_begin, counters, misc, spill, partials, slack_pairs, slack_weights, segments;
+    DevBuf order_keys, order_idx, order_hist, order_items, order_vbegin, queues;
     std::vector<ItemDesc> h_items;
     std::vector<uint32_t> h_task_begin;
     std::vector<unsigned long long> h_partial_off;   // per item, first entry in `partials`
@@ -119,7 +120,7 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
 // S.counts / S.stored / S.error / S.stat.
 hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
                         uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
-                        uint32_t* pairs, float* weights, hipStream_t stream);
+                        bool reorder, uint32_t* pairs, float* weights, hipStream_t stream);
 hrr_status finish_items(hrr_ctx* ctx, LaunchScratch& S, uint32_t* pairs, float* weights, hipStream_t stream);
 
 void release_scratch(LaunchScratch& S);

@@ -397,11 +397,20 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
     O.fill = 0;
     O.count = 0;
 
+    // work queues: start on this block's XCD queue, move on when it is empty
+    uint32_t q = blockIdx.x % kQueues;
+    uint32_t queues_left = kQueues;
     for (;;) {
+        const uint32_t q_lo = (uint32_t)((uint64_t)A.n_tasks * q / kQueues);
+        const uint32_t q_hi = (uint32_t)((uint64_t)A.n_tasks * (q + 1) / kQueues);
         uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(A.task_counter, 1u);
-        t = uni(t);
-        if (t >= A.n_tasks) break;
+        if (lane == 0) t = atomicAdd(A.queues + q * kQueueStride, 1u);
+        t = q_lo + uni(t);
+        if (t >= q_hi) {
+            if (--queues_left == 0) break;
+            q = (q + 1) % kQueues;
+            continue;
+        }
 
         // item of task t: largest k with task_begin[k] <= t
         uint32_t lo = 0, hi = A.n_items;
@@ -424,12 +433,14 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
         // -------- eyes of this task --------
         EyeState E0;   // EPW == 1: wave-uniform eye
         if (EPW == 1) {
-            E0 = load_eye(D, A.tile, u0);
+            const uint32_t u = D.order ? uni(D.order[u0]) : u0;
+            E0 = load_eye(D, A.tile, u);
             E0.ex = unif(E0.ex); E0.ey = unif(E0.ey); E0.ez = unif(E0.ez);
             E0.R = uni(E0.R); E0.kr = uni(E0.kr);
         } else {
             if (lane < cnt) {
-                const EyeState e = load_eye(D, A.tile, u0 + lane);
+                const uint32_t u = D.order ? D.order[u0 + lane] : u0 + lane;
+                const EyeState e = load_eye(D, A.tile, u);
                 uint32_t* w = L.eyes + lane * 8u;
                 w[0] = __float_as_uint(e.ex); w[1] = __float_as_uint(e.ey); w[2] = __float_as_uint(e.ez);
                 w[3] = e.R; w[4] = e.kr; w[5] = e.u;
@@ -609,6 +620,92 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
     }
 }
 
+// ---------------------------------------------------------------------------
+// eye ordering: counting sort of the virtual eyes by (item, Morton cell)
+// ---------------------------------------------------------------------------
+//
+// The traversal result does not depend on the order in which eyes are
+// processed; processing spatially close eyes together lets an XCD's L2 hold
+// the part of the hierarchy they share.  Cells: `bits` bits per axis of the
+// eye position inside the item's light box, interleaved x-y-z; the bucket of
+// virtual eye g of item k is (k << 3 bits) | cell.
+
+__device__ __forceinline__ uint32_t spread3_10(uint32_t v) {
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ __forceinline__ uint32_t cell_of(float x, float lo, float scale, uint32_t bits) {
+    const float f = (x - lo) * scale;
+    const uint32_t top = (1u << bits) - 1u;
+    if (!(f > 0.0f)) return 0u;
+    const float c = floorf(f);
+    return c >= (float)top ? top : (uint32_t)c;
+}
+
+__global__ __launch_bounds__(256) void order_keys_kernel(const OrderItem* __restrict__ items,
+                                                         const uint32_t* __restrict__ vbegin, uint32_t n_items,
+                                                         uint32_t total, uint32_t bits, uint32_t* __restrict__ keys,
+                                                         uint32_t* __restrict__ hist) {
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = n_items;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (vbegin[mid] <= g) lo = mid; else hi = mid;
+        }
+        const OrderItem& I = items[lo];
+        const uint32_t u = g - vbegin[lo];
+        const uint32_t j = I.n_samples > 1 ? u / I.n_samples : u;
+        const float* e = I.eyes + 3u * j;
+        const uint32_t cx = cell_of(e[0], I.lo[0], I.scale[0], bits);
+        const uint32_t cy = cell_of(e[1], I.lo[1], I.scale[1], bits);
+        const uint32_t cz = cell_of(e[2], I.lo[2], I.scale[2], bits);
+        const uint32_t key = (lo << (3u * bits)) | (spread3_10(cx) << 2) | (spread3_10(cy) << 1) | spread3_10(cz);
+        keys[g] = key;
+        atomicAdd(hist + key, 1u);
+    }
+}
+
+// Exclusive prefix sum of n counts in place, one block of 1024 threads.
+__global__ __launch_bounds__(1024) void exclusive_scan_kernel(uint32_t* __restrict__ v, uint32_t n) {
+    __shared__ uint32_t part[1024];
+    const uint32_t per = (n + 1023u) / 1024u;
+    const uint32_t b = threadIdx.x * per;
+    const uint32_t e = min(n, b + per);
+    uint32_t sum = 0;
+    for (uint32_t q = b; q < e; ++q) sum += v[q];
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (uint32_t off = 1; off < 1024u; off <<= 1) {
+        const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - sum;
+    for (uint32_t q = b; q < e; ++q) {
+        const uint32_t x = v[q];
+        v[q] = run;
+        run += x;
+    }
+}
+
+__global__ __launch_bounds__(256) void order_scatter_kernel(const uint32_t* __restrict__ keys,
+                                                            const uint32_t* __restrict__ vbegin, uint32_t total,
+                                                            uint32_t bits, uint32_t* __restrict__ offsets,
+                                                            uint32_t* __restrict__ order) {
+    for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
+        const uint32_t key = keys[g];
+        const uint32_t item = key >> (3u * bits);
+        const uint32_t pos = atomicAdd(offsets + key, 1u);
+        order[pos] = g - vbegin[item];
+    }
+}
+
 // Hole filling after a traversal: segment q copies len[q] pairs (and weights)
 // from position src[q] (the caller's buffer, or the slack area when bit 63 is
 // set) to position dst[q] of the caller's buffer.  Sources and destinations
@@ -652,6 +749,8 @@ extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const
         hipLaunchKernelGGL(hrr::rmq_kernel<1>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     else if (method == 2)
         hipLaunchKernelGGL(hrr::rmq_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
+    else if (method == 3)
+        hipLaunchKernelGGL(hrr::rmq_kernel<3>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     else
         hipLaunchKernelGGL(hrr::rmq_kernel<0>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     return hipGetLastError();
@@ -696,6 +795,7 @@ hipError_t pick_method(const hrr::TravArgs& A, uint32_t method, bool st, bool w,
                        hipStream_t s) {
     if (method == 1) return pick_stats<EPW, 1>(A, st, w, blocks, lds, s);
     if (method == 2) return pick_stats<EPW, 2>(A, st, w, blocks, lds, s);
+    if (method == 3) return pick_stats<EPW, 3>(A, st, w, blocks, lds, s);
     return pick_stats<EPW, 0>(A, st, w, blocks, lds, s);
 }
 
@@ -731,7 +831,7 @@ extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t me
     if (eyes_per_wave == E && method == M && (stats != 0) == S && (with_weights != 0) == W) \
         f = (const void*)hrr::traverse_kernel<E, M, S, W>;
 #define HRR_PICK_SW(E, M) HRR_PICK(E, M, false, false) HRR_PICK(E, M, false, true) HRR_PICK(E, M, true, false) HRR_PICK(E, M, true, true)
-#define HRR_PICK_M(E) HRR_PICK_SW(E, 0) HRR_PICK_SW(E, 1) HRR_PICK_SW(E, 2)
+#define HRR_PICK_M(E) HRR_PICK_SW(E, 0) HRR_PICK_SW(E, 1) HRR_PICK_SW(E, 2) HRR_PICK_SW(E, 3)
     HRR_PICK_M(1) HRR_PICK_M(2) HRR_PICK_M(4) HRR_PICK_M(8)
 #undef HRR_PICK_M
 #undef HRR_PICK_SW
@@ -743,4 +843,24 @@ extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t me
     }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, hrr::kWave * hrr::kWavesPerBlock,
                                                         lds_per_block);
+}
+
+// Processing order of the virtual eyes of a launch (see order_keys_kernel).
+// hist must hold n_items << (3 bits) counters; keys and order `total` words.
+extern "C" hipError_t hrr_launch_order(const hrr::OrderItem* items, const uint32_t* vbegin, uint32_t n_items,
+                                       uint32_t total, uint32_t bits, uint32_t* keys, uint32_t* hist, uint32_t* order,
+                                       int n_cu, hipStream_t stream) {
+    if (total == 0) return hipSuccess;
+    const uint32_t n_buckets = n_items << (3u * bits);
+    hipError_t e = hipMemsetAsync(hist, 0, (size_t)n_buckets * sizeof(uint32_t), stream);
+    if (e != hipSuccess) return e;
+    uint32_t blocks = (total + 255u) / 256u;
+    const uint32_t max_blocks = (uint32_t)(n_cu > 0 ? n_cu : 256) * 8u;
+    if (blocks > max_blocks) blocks = max_blocks;
+    hipLaunchKernelGGL(hrr::order_keys_kernel, dim3(blocks), dim3(256), 0, stream, items, vbegin, n_items, total, bits,
+                       keys, hist);
+    hipLaunchKernelGGL(hrr::exclusive_scan_kernel, dim3(1), dim3(1024), 0, stream, hist, n_buckets);
+    hipLaunchKernelGGL(hrr::order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, keys, vbegin, total, bits, hist,
+                       order);
+    return hipGetLastError();
 }

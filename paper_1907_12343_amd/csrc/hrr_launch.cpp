@@ -16,6 +16,9 @@ extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap);
 extern "C" size_t hrr_trav_lds_per_block(uint32_t n_items, size_t lds_per_wave);
 extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t method, int stats, int with_weights,
                                              size_t lds_per_block, int* blocks_per_cu);
+extern "C" hipError_t hrr_launch_order(const hrr::OrderItem* items, const uint32_t* vbegin, uint32_t n_items,
+                                       uint32_t total, uint32_t bits, uint32_t* keys, uint32_t* hist, uint32_t* order,
+                                       int n_cu, hipStream_t stream);
 extern "C" hipError_t hrr_launch_move_pairs(const unsigned long long* seg, uint32_t n_seg, uint32_t* pairs,
                                             float* weights, const uint32_t* slack_pairs, const float* slack_weights,
                                             hipStream_t stream);
@@ -32,7 +35,7 @@ constexpr unsigned long long kSlackFlag = 1ull << 63;
 
 hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
                         uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
-                        uint32_t* pairs, float* weights, hipStream_t stream) {
+                        bool reorder, uint32_t* pairs, float* weights, hipStream_t stream) {
     const size_t n = items.size();
     if (n == 0 || n > kMaxItemsPerLaunch)
         return fail(HRR_E_INVALID, "items per launch must be in [1, %u]", kMaxItemsPerLaunch);
@@ -40,7 +43,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         return fail(HRR_E_INVALID, "eyes_per_wave must be 1, 2, 4 or 8");
     if (!is_pow2(cap) || cap < 256 || cap > 4096)
         return fail(HRR_E_INVALID, "stack_entries must be a power of two in [256, 4096]");
-    if (method > 2) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
+    if (method > 3) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
     if (n_samples == 0) n_samples = 1;
     const int with_w = weights != nullptr;
 
@@ -98,6 +101,42 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         partial_total += wk;
     }
 
+    // ---- eye processing order: counting sort by (item, Morton cell) ----
+    std::vector<uint32_t> vbegin(n + 1, 0);
+    uint64_t vtotal = 0;
+    for (size_t k = 0; k < n; ++k) {
+        vbegin[k] = (uint32_t)std::min<uint64_t>(vtotal, 0xFFFFFFFFull);
+        vtotal += items[k].h->n_lights ? (uint64_t)items[k].eyes.n * n_samples : 0ull;
+    }
+    vbegin[n] = (uint32_t)std::min<uint64_t>(vtotal, 0xFFFFFFFFull);
+    uint32_t bits = 0;
+    if (reorder && vtotal > 0 && vtotal < 0xFFFFFFFFull)
+        while (bits < 10 && ((uint64_t)n << (3 * (bits + 1))) <= kOrderMaxBuckets) ++bits;
+    const bool ordered = bits > 0;
+    std::vector<OrderItem> oitems;
+    if (ordered) {
+        oitems.resize(n);
+        for (size_t k = 0; k < n; ++k) {
+            const hrr_hierarchy* h = items[k].h;
+            OrderItem& o = oitems[k];
+            o.eyes = items[k].eyes.xyz;
+            o.n_samples = n_samples;
+            o.pad = 0;
+            for (int q = 0; q < 3; ++q) {
+                const float ext = h->box[3 + q] - h->box[q];
+                o.lo[q] = h->box[q];
+                o.scale[q] = ext > 0.0f ? (float)(1u << bits) / ext : 0.0f;
+            }
+        }
+        if ((e = S.order_keys.ensure(vtotal * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "order keys");
+        if ((e = S.order_idx.ensure(vtotal * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "eye order");
+        if ((e = S.order_hist.ensure(((size_t)n << (3 * bits)) * sizeof(uint32_t))) != hipSuccess)
+            return hip_fail(e, "order histogram");
+        if ((e = S.order_items.ensure(n * sizeof(OrderItem))) != hipSuccess) return hip_fail(e, "order items");
+        if ((e = S.order_vbegin.ensure((n + 1) * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "order offsets");
+    }
+    if ((e = S.queues.ensure(kQueues * kQueueStride * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "queues");
+
     S.n_items = n;
     S.with_weights = with_w;
     S.stats = stats;
@@ -128,6 +167,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         D.weights = weights ? weights + it.out_offset : nullptr;
         D.slack_pairs = static_cast<uint32_t*>(S.slack_pairs.p) + 2 * m.slack_off;
         D.slack_weights = with_w ? static_cast<float*>(S.slack_weights.p) + m.slack_off : nullptr;
+        D.order = ordered ? static_cast<const uint32_t*>(S.order_idx.p) + vbegin[k] : nullptr;
         D.counters = d_counters + k * CNT_STRIDE;
         D.partials = d_partials + 2 * m.partial_off;
         D.capacity = it.out_capacity;
@@ -157,8 +197,10 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     // pinned staging: readback words first, then the upload of the tables
     const size_t items_bytes = n * sizeof(ItemDesc);
     const size_t tb_bytes = (n + 1) * sizeof(uint32_t);
+    const size_t oi_bytes = ordered ? n * sizeof(OrderItem) : 0;
+    const size_t vb_bytes = ordered ? (n + 1) * sizeof(uint32_t) : 0;
     const size_t read_words = n * CNT_STRIDE + 1 + ST_N;
-    const size_t pin_words = read_words + (items_bytes + tb_bytes + 7) / 8 + 2;
+    const size_t pin_words = read_words + (items_bytes + tb_bytes + oi_bytes + vb_bytes + 7) / 8 + 8;
     if (S.h_pinned_n < pin_words) {
         if (S.h_pinned) (void)hipHostFree(S.h_pinned);
         S.h_pinned = nullptr;
@@ -170,6 +212,13 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     unsigned char* up = reinterpret_cast<unsigned char*>(S.h_pinned + read_words);
     memcpy(up, S.h_items.data(), items_bytes);
     memcpy(up + items_bytes, S.h_task_begin.data(), tb_bytes);
+    // OrderItem holds a pointer: keep it 8-byte aligned
+    const size_t oi_at = (items_bytes + tb_bytes + 7) / 8 * 8;
+    const size_t vb_at = oi_at + oi_bytes;
+    if (ordered) {
+        memcpy(up + oi_at, oitems.data(), oi_bytes);
+        memcpy(up + vb_at, vbegin.data(), vb_bytes);
+    }
 
     if ((e = S.items.ensure(items_bytes)) != hipSuccess) return hip_fail(e, "item table");
     if ((e = S.task_begin.ensure(tb_bytes)) != hipSuccess) return hip_fail(e, "task table");
@@ -181,6 +230,19 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         return hip_fail(e, "clear counters");
     if ((e = hipMemsetAsync(d_misc, 0, 16 * sizeof(unsigned long long), stream)) != hipSuccess)
         return hip_fail(e, "clear misc");
+    if ((e = hipMemsetAsync(S.queues.p, 0, kQueues * kQueueStride * sizeof(uint32_t), stream)) != hipSuccess)
+        return hip_fail(e, "clear queues");
+    if (ordered) {
+        if ((e = hipMemcpyAsync(S.order_items.p, up + oi_at, oi_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "upload order items");
+        if ((e = hipMemcpyAsync(S.order_vbegin.p, up + vb_at, vb_bytes, hipMemcpyHostToDevice, stream)) != hipSuccess)
+            return hip_fail(e, "upload order offsets");
+        if ((e = hrr_launch_order(static_cast<const OrderItem*>(S.order_items.p),
+                                  static_cast<const uint32_t*>(S.order_vbegin.p), (uint32_t)n, (uint32_t)vtotal, bits,
+                                  static_cast<uint32_t*>(S.order_keys.p), static_cast<uint32_t*>(S.order_hist.p),
+                                  static_cast<uint32_t*>(S.order_idx.p), ctx->n_cu, stream)) != hipSuccess)
+            return hip_fail(e, "eye ordering");
+    }
 
     if (tasks > 0) {
         const uint32_t half = cap / 2;
@@ -195,7 +257,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         A.task_begin = static_cast<const uint32_t*>(S.task_begin.p);
         A.n_items = (uint32_t)n;
         A.n_tasks = (uint32_t)tasks;
-        A.task_counter = reinterpret_cast<uint32_t*>(d_misc + 0);
+        A.queues = static_cast<uint32_t*>(S.queues.p);
         A.tile = ctx->d_tile;
         A.spill = static_cast<unsigned long long*>(S.spill.p);
         A.spill_cap = spill_cap;

@@ -24,7 +24,7 @@
 //       Section 2's "right-to-left" sweep reaches by trying exactly i
 //       trailing zeros for i = 0, 1, ...
 //
-// Three implementations compute the same k:
+// Four implementations compute the same k:
 //   rmq_paper  -- the paper's method: case test, left-to-right sweep with
 //                 refinement, right-to-left sweep.  Written from the paper's
 //                 description with gfx950-friendly changes that keep the
@@ -37,10 +37,14 @@
 //                 case a == 0 with no index above the threshold returns 0, the
 //                 reflected-smallest index overall (the printed sweep stops at
 //                 i = B - 1 and would miss it).
-//   rmq_paper_pruned -- the same sweeps, refining only the one candidate
-//                 whose prefix class meets [a,b) (the default).
+//   rmq_paper_pruned -- the same sweeps as loops, refining only the one
+//                 candidate whose prefix class meets [a,b).
+//   rmq_paper_select -- the same sweeps with every candidate position tested
+//                 at once by bit arithmetic, then Algorithm 3's refinement of
+//                 the winning prefix class (the default: no divergent scan
+//                 loops on the VALU, only the short refinement walk).
 //   rmq_direct -- the same three cases, each resolved in O(1) bit
-//                 arithmetic (an ablation of the sweep, no loops).
+//                 arithmetic, refinement included (an ablation, no loops).
 //
 // All functions are __host__ __device__ so that host-side unit harnesses can
 // exercise exactly the code the kernels run.
@@ -229,13 +233,54 @@ HRR_HD uint32_t rmq_direct(uint32_t a, uint32_t b, uint32_t kr) {
     return most_trailing_zeros(a, b - 1u);
 }
 
-// METHOD 0: the paper's sweeps with pruning (default); 1: O(1) ablation;
-// 2: the paper's sweeps refining every candidate (ablation).
+// The paper's method with both sweeps evaluated for all bit positions at
+// once.  The sweeps look for the highest zero bit i of k_r whose prefix class
+// (k_r's bits below i, a 1 at i) meets [a,b); left-to-right positions
+// (>= k_p) outrank right-to-left ones (< k_p) and higher outranks lower, so
+// the winner is simply the highest such bit.  With g the top bit of b - a:
+// above g a class meets the range only at the lowest set bit of k_r - a above
+// g (one member, a + ((k_r - a + 2^i) mod 2^(i+1))); at g the same single-
+// member test applies; below g every class meets the range, so the highest
+// zero bit of k_r below g wins and Algorithm 3's refinement walks it to its
+// reflected-smallest member.  No class: the range's reflected-smallest index,
+// the one with the most trailing zeros (Algorithm 1's answer).
+HRR_HD uint32_t rmq_paper_select(uint32_t a, uint32_t b, uint32_t kr) {
+    if (in_range(kr, a, b)) return kr;
+    const uint32_t len = b - a;
+    const int g = top_bit(len);
+    const uint32_t d = kr - a;
+    const uint32_t dlow = d & low_mask(g + 1);
+    if (g < 31) {
+        const uint32_t dhi = d >> (g + 1);
+        if (dhi) {
+            const int i = bottom_bit(dhi) + g + 1;
+            if (!((kr >> i) & 1u) && dlow < len) return a + ((d & low_mask(i + 1)) ^ (1u << i));
+        }
+    }
+    if (!((kr >> g) & 1u)) {
+        const uint32_t t = dlow ^ (1u << g);
+        if (t < len) return a + t;
+    }
+    const uint32_t z = ~kr & low_mask(g);
+    if (z) {
+        const int i = top_bit(z);
+        return refine(seed_candidate(a, i, kr & low_mask(i)), i + 1, a, b);
+    }
+    return most_trailing_zeros(a, b - 1u);
+}
+
+// METHOD 0: the paper's sweeps, candidate positions selected bit-parallel,
+//           Algorithm 3 refinement (default);
+//        1: closed form of every step (ablation, no refinement walk);
+//        2: the paper's sweeps refining every candidate in turn (ablation);
+//        3: the paper's sweeps as loops, refining only the candidate that
+//           meets the range (ablation).
 template <int METHOD>
 HRR_HD uint32_t rmq(uint32_t a, uint32_t b, uint32_t kr) {
     if (METHOD == 1) return rmq_direct(a, b, kr);
     if (METHOD == 2) return rmq_paper(a, b, kr);
-    return rmq_paper_pruned(a, b, kr);
+    if (METHOD == 3) return rmq_paper_pruned(a, b, kr);
+    return rmq_paper_select(a, b, kr);
 }
 
 }  // namespace hrr

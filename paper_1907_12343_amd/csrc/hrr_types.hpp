@@ -37,6 +37,7 @@ struct ItemDesc {
     float* weights;               // item's weight slice or null
     uint32_t* slack_pairs;        // positions >= capacity land here (library memory)
     float* slack_weights;
+    const uint32_t* order;        // processing order of the virtual eyes, or null (index order)
     unsigned long long* counters; // CNT_PAIRS, CNT_CHUNKS, CNT_PARTIALS (device)
     unsigned long long* partials; // (chunk, fill) of partly filled chunks
     unsigned long long capacity;  // pairs the slice can hold
@@ -49,6 +50,15 @@ struct ItemDesc {
     float root_lo[3], root_hi[3];
 };
 
+// Eye-ordering description of one item: eyes are bucketed by the Morton
+// cell of their position inside the item's light box (cell = (x - lo) * scale,
+// clamped), so that consecutive tasks walk nearby parts of the hierarchy.
+struct OrderItem {
+    const float* eyes;
+    float lo[3], scale[3];
+    uint32_t n_samples, pad;
+};
+
 // Per-item device counters, one 128-byte line per item.
 enum CounterIdx { CNT_PAIRS = 0, CNT_CHUNKS = 1, CNT_PARTIALS = 2, CNT_STRIDE = 16 };
 
@@ -57,7 +67,7 @@ struct TravArgs {
     const ItemDesc* items;
     const uint32_t* task_begin;   // n_items + 1 prefix of tasks per item
     uint32_t n_items, n_tasks;
-    uint32_t* task_counter;       // device work queue head
+    uint32_t* queues;             // kQueues work-queue heads, kQueueStride words apart
     const uint32_t* tile;         // 64 x 64 shifts
     unsigned long long* spill;    // per-wave spill stacks (uint2 entries)
     uint32_t spill_cap;           // entries per wave
@@ -71,6 +81,13 @@ struct TravArgs {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr uint32_t kMaxItemsPerLaunch = 1024;
+// One work queue per XCD: queue q owns tasks [q T / 8, (q+1) T / 8); blocks
+// are dispatched to the 8 XCDs round-robin, so block b starts on queue b % 8
+// and its L2 sees a contiguous (spatially ordered) slice of the eyes.
+constexpr uint32_t kQueues = 8;
+constexpr uint32_t kQueueStride = 32;   // 128 bytes between queue heads
+// Eye ordering: counting sort over (item, Morton cell) buckets.
+constexpr uint32_t kOrderMaxBuckets = 1u << 20;
 constexpr uint32_t kMinChunkShift = 6;  // a chunk holds >= 64 pairs (one emission step)
 constexpr uint32_t kMaxChunkShift = 13;
 constexpr uint32_t kSlotShift = 28;     // stack entry: node | slot << 28

@@ -11,7 +11,7 @@ import synth
 pytestmark = pytest.mark.gpu
 
 M32 = 0xFFFFFFFF
-METHODS = [0, 1, 2]   # pruned paper sweep (default), O(1) ablation, unpruned sweep
+METHODS = [0, 1, 2, 3]   # paper (default), closed form, unpruned sweep, pruned loop sweep
 
 
 @pytest.fixture(scope="module")

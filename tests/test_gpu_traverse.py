@@ -52,7 +52,7 @@ def test_light_order_matches_oracle(ctx, orc, tiny, tiny_oracle):
         h.free()
 
 
-@pytest.mark.parametrize("method", [0, 1, 2])
+@pytest.mark.parametrize("method", [0, 1, 2, 3])
 @pytest.mark.parametrize("leaf", [1, 2, 4, 8])
 @pytest.mark.parametrize("epw", [1, 2, 4, 8])
 def test_tiny_full_parity(ctx, tiny, tiny_oracle, method, leaf, epw):
@@ -82,11 +82,26 @@ def test_stack_spills_to_device_memory(ctx, orc):
     sel = np.arange(0, 512, 5)
     out = orc.accept_eyes(eyes, sel, 64, 0, tile, h.sorted_lights(), s, lists=True)
     assert np.array_equal(select_pairs_of_eyes(pairs, sel), pair_keys_from_oracle(out, sel))
-    # same set with a roomy stack and several eyes per wave
+    # same set with a roomy stack and several eyes per wave, and in index order
     p2, n2, st2 = ctx.traverse_all(h, _eyes_t(ctx, eyes), s, 64, stack_entries=2048,
                                    eyes_per_wave=4, stats=True)
     assert n2 == n
     assert np.array_equal(pair_keys_from_gpu(p2), pair_keys_from_gpu(pairs))
+    p3, n3, _ = ctx.traverse_all(h, _eyes_t(ctx, eyes), s, 64, reorder=False)
+    assert n3 == n
+    assert np.array_equal(pair_keys_from_gpu(p3), pair_keys_from_gpu(pairs))
+    h.free()
+
+
+@pytest.mark.parametrize("epw", [1, 8])
+def test_processing_order_does_not_change_the_set(ctx, tiny, tiny_oracle, epw):
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=2)
+    eyes = _eyes_t(ctx, tiny["eyes"])
+    for reorder in (True, False):
+        pairs, n, st = ctx.traverse_all(h, eyes, tiny["s"], tiny["width"], eyes_per_wave=epw,
+                                        reorder=reorder, stats=True)
+        assert np.array_equal(pair_keys_from_gpu(pairs), tiny_oracle["keys"])
+        assert st["eyes"] == tiny["eyes"].shape[0]
     h.free()
 
 
