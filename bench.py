@@ -28,20 +28,21 @@ HBM_PEAK_GBS = 8000.0
 # non-packed 32-bit VALU issue: 256 CU x 64 lanes x 2.4 GHz
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
-# Algorithmic 32-bit VALU operations per unit of traversal work (counted from
-# the arithmetic of each unit as gfx950 executes it):
-#   visit : one internal node popped -- both children's box distances
-#           (2 x 17), acceptance probabilities with IEEE division and margin
-#           (2 x 12), fixed-point keep tests (2 x 5), inherited-minimum
-#           selection and rotated values (8), push/emit compaction (12)
-#   rmq   : one range-minimum query with the paper's method, per loop trip
-#           of its sweeps and refinement (10) plus set-up (12)
-#   leaf  : one exact per-light test of a multi-light leaf (light fetch
-#           excluded): distance 9, probability 12, keep test 5, emission 4
-OPS_VISIT = 34 + 24 + 10 + 8 + 12
-OPS_RMQ_SETUP = 12
-OPS_RMQ_TRIP = 10
+# Algorithmic 32-bit VALU lane-operations per unit of traversal work, counted
+# from the arithmetic each unit needs as gfx950 executes it (the design doc lists
+# the count):
+#   visit : one internal node popped, both children bounded -- inherited
+#           minimum selection 5; per child 34 (box distance 9, squares and sum
+#           5, IEEE division 10, margin and min 3, fixed-point keep test 5,
+#           rotated value 2); survivor/leaf decisions 8; ballot compaction 8
+#   rmq   : one range minimum with the default method (case test, bit-parallel
+#           flip-position selection, seed and about two refinement steps)
+#   leaf  : one exact test of a light inside a multi-light leaf
+#   pair  : one emitted pair (compaction, position, store address)
+OPS_VISIT = 5 + 2 * 34 + 8 + 8
+OPS_RMQ = 40
 OPS_LEAF = 30
+OPS_PAIR = 6
 BYTES_PER_QUERY = 20   # range minimum: a, b, r in; argmin, min out
 
 
@@ -86,9 +87,9 @@ def frame_workload(args):
     ms = (t1 - t0) * 1e3 / args.steps
     gpu_ms = e0.elapsed_time(e1) / args.steps
 
-    trips = st.get("rmq_trips", 0)
-    ops = (st["node_visits"] * OPS_VISIT + st["rmq_calls"] * OPS_RMQ_SETUP
-           + trips * OPS_RMQ_TRIP + max(st["leaf_tests"] - 2 * st["node_visits"], 0) * OPS_LEAF)
+    multi_leaf_tests = max(st["leaf_tests"] - 2 * st["node_visits"], 0)
+    ops = (st["node_visits"] * OPS_VISIT + st["rmq_calls"] * OPS_RMQ + multi_leaf_tests * OPS_LEAF
+           + n * OPS_PAIR)
     achieved = ops / (gpu_ms * 1e-3) / 1e12
     line = {
         "metric": "eye-vertex traversals/s",
@@ -112,10 +113,12 @@ def frame_workload(args):
         "kernel_ms": gpu_ms,
         "hierarchy_build_s": build_s,
         "units": {"node_visits": st["node_visits"], "rmq_calls": st["rmq_calls"],
-                  "leaf_tests": st["leaf_tests"], "rmq_trips": trips},
+                  "leaf_tests": st["leaf_tests"], "pairs": n},
+        "algorithmic_lane_ops": ops,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None},
+                     "traffic": (None if args.traffic_kib is None
+                                 else (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0)},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_frame(fr, h.permutation(), n_eyes, args)
@@ -203,6 +206,10 @@ def main():
     p.add_argument("--rmq", default="paper", choices=["paper", "direct"])
     p.add_argument("--epw", type=int, default=1)
     p.add_argument("--stack", type=int, default=512)
+    p.add_argument("--traffic-kib", type=float, nargs=2, default=None,
+                   metavar=("FETCH", "WRITE"),
+                   help="FETCH_SIZE and WRITE_SIZE (KiB per launch) of the traversal kernel "
+                        "from rocprofv3 --pmc runs, already scaled by the copy-kernel factors")
     p.add_argument("--cpu-eyes", type=int, default=256)
     p.add_argument("--no-cpu-baseline", action="store_true")
     args = p.parse_args()

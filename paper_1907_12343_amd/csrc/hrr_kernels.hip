@@ -17,7 +17,7 @@
 // pushed back with ballot/mbcnt compaction.  Leaves with one light are tested
 // exactly at the parent; accepted pairs go straight from the lanes into an
 // output chunk the wave owns (one atomic per chunk of thousands of pairs, see
-// emit_put).  The stack spills in halves to a per-wave region
+// emit2).  The stack spills in halves to a per-wave region
 // of device memory when it would overflow LDS; its size is bounded by
 // 128 entries per tree level (see stack_spill).
 //
@@ -95,6 +95,39 @@ __device__ __forceinline__ bool keeps(uint32_t v, float p) {
 }
 
 constexpr float kBoxMargin = 1.0f + 0x1p-20f;
+
+// ---- fast bounds with v_rcp_f32 --------------------------------------------
+//
+// The IEEE quotient s / d2 costs about ten VALU instructions.  v_rcp_f32
+// returns 1/d2 within 1 ulp (relative error <= 2^-23, CDNA ISA), so
+// q' = s * rcp(d2) is within 2^-23 + 2^-24 of s / d2 and within ~2^-22 of the
+// rounded quotient.  Comparing the fixed-point random number against q' 2^32
+// with a relative band of 2^-19 on either side therefore decides the exact
+// test whenever the value lies outside the band; inside it (about 2^-18 of the
+// cases) the exact IEEE path decides.  Extreme magnitudes (d2 > 2^100 or
+// q' < 2^-60, never met in the unit cube) always take the exact path so that
+// no underflow of rcp can flip a decision.
+constexpr float kTwo32Lo = 0x1p32f * (1.0f - 0x1p-19f);
+constexpr float kTwo32Hi = 0x1p32f * (1.0f + 0x1p-19f);
+
+// Keep test of value v at squared distance d2.
+//   exact = true : one light; the result equals keeps(v, min(1, s / d2)).
+//   exact = false: a box; false only if no light in the box can keep v.  It
+//                  culls only when (float)v exceeds q' 2^32 (1 + 2^-19), which
+//                  implies v > p 2^32 for every light at distance^2 >= d2.
+// d2 <= s means s / d2 >= 1 (p = 1): always kept.
+__device__ __forceinline__ bool rr_test(uint32_t v, float s, float d2, bool exact) {
+    if (d2 <= s) return true;
+    if (d2 <= 0x1p100f) {
+        const float q = s * __builtin_amdgcn_rcpf(d2);
+        if (q >= 0x1p-60f) {
+            const float V = (float)v;
+            if (V > q * kTwo32Hi) return false;
+            if (!exact || V < q * kTwo32Lo) return true;
+        }
+    }
+    return keeps(v, accept_p(s, d2, exact ? 1.0f : kBoxMargin));
+}
 
 // Fixed-point golden-ratio lattice alpha = round(2^32 (sqrt(5) - 1) / 2).
 constexpr uint32_t kGoldenAlpha = 2654435769u;
@@ -250,8 +283,10 @@ __device__ __forceinline__ void stack_refill(StackState& st, const WaveLds& L, c
 constexpr unsigned long long kNoChunk = ~0ull;
 
 struct OutState {
-    unsigned long long chunk;
-    unsigned long long count;
+    unsigned long long chunk;   // current chunk, or kNoChunk
+    unsigned long long count;   // pairs emitted for the current item
+    uint2* wp;                  // first pair slot of the chunk when it lies wholly in one buffer
+    float* ww;                  // same for the weights
     uint32_t fill;
 };
 
@@ -263,6 +298,26 @@ __device__ __forceinline__ unsigned long long alloc_chunk(const ItemDesc& D) {
     unsigned long long c = 0;
     if (lane_id() == 0) c = atomicAdd(D.counters + CNT_CHUNKS, 1ull);
     return uni64(c);
+}
+
+// Make `c` the current chunk; direct pointers when the whole chunk lies below
+// the capacity or inside the slack area (a chunk that straddles the capacity
+// or the end of the slack takes the per-pair path).
+template <bool W>
+__device__ __forceinline__ void set_chunk(OutState& O, const ItemDesc& D, unsigned long long c) {
+    O.chunk = c;
+    O.wp = nullptr;
+    O.ww = nullptr;
+    if (c == kNoChunk) return;
+    const unsigned long long p0 = c << D.chunk_shift;
+    const unsigned long long C = 1ull << D.chunk_shift;
+    if (p0 + C <= D.capacity) {
+        O.wp = reinterpret_cast<uint2*>(D.pairs) + p0;
+        if (W) O.ww = D.weights + p0;
+    } else if (p0 >= D.capacity && p0 - D.capacity + C <= D.slack) {
+        O.wp = reinterpret_cast<uint2*>(D.slack_pairs) + (p0 - D.capacity);
+        if (W) O.ww = D.slack_weights + (p0 - D.capacity);
+    }
 }
 
 template <bool W>
@@ -277,30 +332,48 @@ __device__ __forceinline__ void store_pair(const ItemDesc& D, unsigned long long
     }
 }
 
-// Emit at most one pair per lane (uniform control flow).
+// Emit up to two pairs per lane (the first before the second), compacted over
+// the wave (uniform control flow).  A step holds at most 128 pairs and a chunk
+// at least 128, so a step crosses at most one chunk boundary.
 template <bool W>
-__device__ __forceinline__ void emit_put(OutState& O, const ItemDesc& D, bool emit, uint32_t u, uint32_t i, float w) {
-    const uint64_t m = ballot(emit);
-    const uint32_t cnt = (uint32_t)__popcll(m);
+__device__ __forceinline__ void emit2(OutState& O, const ItemDesc& D, bool e0, uint2 p0, float w0, bool e1, uint2 p1,
+                                      float w1) {
+    const uint64_t m0 = ballot(e0), m1 = ballot(e1);
+    const uint32_t cnt = (uint32_t)(__popcll(m0) + __popcll(m1));
     if (cnt == 0) return;
+    if (O.chunk == kNoChunk) {
+        set_chunk<W>(O, D, alloc_chunk(D));
+        O.fill = 0;
+    }
     const uint32_t shift = D.chunk_shift;
     const uint32_t C = 1u << shift;
-    if (O.chunk == kNoChunk) {
-        O.chunk = alloc_chunk(D);
-        O.fill = 0;
+    const uint32_t pos0 = O.fill + count_below(m0) + count_below(m1);
+    const uint32_t pos1 = pos0 + (e0 ? 1u : 0u);
+    if (O.wp && O.fill + cnt <= C) {
+        if (e0) {
+            O.wp[pos0] = p0;
+            if (W) O.ww[pos0] = w0;
+        }
+        if (e1) {
+            O.wp[pos1] = p1;
+            if (W) O.ww[pos1] = w1;
+        }
+        O.fill += cnt;
+        O.count += cnt;
+        if (O.fill == C) set_chunk<W>(O, D, kNoChunk);
+        return;
     }
     unsigned long long next = kNoChunk;
     if (O.fill + cnt > C) next = alloc_chunk(D);
-    if (emit) {
-        const uint32_t pos = O.fill + count_below(m);
-        const unsigned long long p = pos < C ? (O.chunk << shift) + pos : (next << shift) + (pos - C);
-        store_pair<W>(D, p, make_uint2(u, i), w);
-    }
+    const unsigned long long base = O.chunk << shift;
+    const unsigned long long nbase = next << shift;
+    if (e0) store_pair<W>(D, pos0 < C ? base + pos0 : nbase + (pos0 - C), p0, w0);
+    if (e1) store_pair<W>(D, pos1 < C ? base + pos1 : nbase + (pos1 - C), p1, w1);
     O.count += cnt;
     O.fill += cnt;
     if (O.fill >= C) {
-        O.chunk = next;
         O.fill -= C;
+        set_chunk<W>(O, D, next);
     }
 }
 
@@ -319,6 +392,8 @@ __device__ __forceinline__ void close_item(OutState& O, const ItemDesc& D, uint3
         if (O.count) atomicAdd(D.counters + CNT_PAIRS, O.count);
     }
     O.chunk = kNoChunk;
+    O.wp = nullptr;
+    O.ww = nullptr;
     O.fill = 0;
     O.count = 0;
 }
@@ -358,12 +433,11 @@ __device__ __forceinline__ void leaf_lights(OutState& O, const ItemDesc& D, cons
             i = q < ln ? la + q : ra + (q - ln);
             const float4 P = reinterpret_cast<const float4*>(D.lights)[i];
             const float d2 = box_d2(E.ex, E.ey, E.ez, P.x, P.y, P.z, P.x, P.y, P.z);
-            const float p = accept_p(D.s, d2, 1.0f);
-            emit = keeps(rotated(i, E.R), p);
-            if (W) w = 1.0f / p;
+            emit = rr_test(rotated(i, E.R), D.s, d2, true);
+            if (W) w = 1.0f / accept_p(D.s, d2, 1.0f);
             ++tests;
         }
-        emit_put<W>(O, D, emit, E.u, i, w);
+        emit2<W>(O, D, emit, make_uint2(E.u, i), w, false, make_uint2(0u, 0u), 0.0f);
     }
 }
 
@@ -394,6 +468,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
     ItemDesc D;
     OutState O;
     O.chunk = kNoChunk;
+    O.wp = nullptr;
+    O.ww = nullptr;
     O.fill = 0;
     O.count = 0;
 
@@ -472,12 +548,11 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
                     if (a1) {
                         const float4 P = reinterpret_cast<const float4*>(D.lights)[lane];
                         const float d2 = box_d2(E.ex, E.ey, E.ez, P.x, P.y, P.z, P.x, P.y, P.z);
-                        const float p = accept_p(s, d2, 1.0f);
-                        emit = keeps(rotated(lane, E.R), p);
-                        if (W) w = 1.0f / p;
+                        emit = rr_test(rotated(lane, E.R), s, d2, true);
+                        if (W) w = 1.0f / accept_p(s, d2, 1.0f);
                         ++tests;
                     }
-                    emit_put<W>(O, D, emit, E.u, lane, w);
+                    emit2<W>(O, D, emit, make_uint2(E.u, lane), w, false, make_uint2(0u, 0u), 0.0f);
                 } else {
                     leaf_lights<W>(O, D, E, 0u, act ? N : 0u, 0u, 0u, tests);
                 }
@@ -490,7 +565,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
                 k0 = rmq<METHOD>(0u, N, E.kr);
                 const float d2 = box_d2(E.ex, E.ey, E.ez, D.root_lo[0], D.root_lo[1], D.root_lo[2],
                                         D.root_hi[0], D.root_hi[1], D.root_hi[2]);
-                push = keeps(rotated(k0, E.R), accept_p(s, d2, kBoxMargin));
+                push = rr_test(rotated(k0, E.R), s, d2, false);
                 if (STATS) ++st_rmq;
             }
             const uint64_t m = ballot(push);
@@ -550,15 +625,16 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
                 const bool leafL = nL <= leaf, leafR = nR <= leaf;
                 const float d2L = box_d2(E.ex, E.ey, E.ez, q0.x, q0.y, q0.z, q1.x, q1.y, q1.z);
                 const float d2R = box_d2(E.ex, E.ey, E.ez, q2.x, q2.y, q2.z, q3.x, q3.y, q3.z);
-                const float pL = accept_p(s, d2L, nL == 1u ? 1.0f : kBoxMargin);
-                const float pR = accept_p(s, d2R, nR == 1u ? 1.0f : kBoxMargin);
-                const bool sL = keeps(rotated(kL, E.R), pL);
-                const bool sR = keeps(rotated(kR, E.R), pR);
+                const bool sL = rr_test(rotated(kL, E.R), s, d2L, nL == 1u);
+                const bool sR = rr_test(rotated(kR, E.R), s, d2R, nR == 1u);
                 pushL = sL && !leafL;
                 pushR = sR && !leafR;
                 emitL = sL && nL == 1u;
                 emitR = sR && nR == 1u;
-                if (W) { wL = 1.0f / pL; wR = 1.0f / pR; }
+                if (W) {
+                    if (emitL) wL = 1.0f / accept_p(s, d2L, 1.0f);
+                    if (emitR) wR = 1.0f / accept_p(s, d2R, 1.0f);
+                }
                 if (sL && leafL && nL > 1u) { mlA = a; mlN = nL; }
                 if (sR && leafR && nR > 1u) { mrA = c; mrN = nR; }
                 if (STATS) st_leaf += (uint64_t)(nL == 1u) + (uint64_t)(nR == 1u);
@@ -582,8 +658,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
             }
 
             // one-light leaves accepted at the parent
-            emit_put<W>(O, D, emitL, E.u, a, wL);
-            emit_put<W>(O, D, emitR, E.u, c, wR);
+            emit2<W>(O, D, emitL, make_uint2(E.u, a), wL, emitR, make_uint2(E.u, c), wR);
 
             // multi-light leaves
             if (ballot(mlN + mrN > 0u)) {

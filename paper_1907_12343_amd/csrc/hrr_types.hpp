@@ -88,7 +88,7 @@ constexpr uint32_t kQueues = 8;
 constexpr uint32_t kQueueStride = 32;   // 128 bytes between queue heads
 // Eye ordering: counting sort over (item, Morton cell) buckets.
 constexpr uint32_t kOrderMaxBuckets = 1u << 20;
-constexpr uint32_t kMinChunkShift = 6;  // a chunk holds >= 64 pairs (one emission step)
+constexpr uint32_t kMinChunkShift = 7;  // a chunk holds >= 128 pairs (one emission step)
 constexpr uint32_t kMaxChunkShift = 13;
 constexpr uint32_t kSlotShift = 28;     // stack entry: node | slot << 28
 constexpr uint32_t kMaxNodes = 1u << kSlotShift;

@@ -186,6 +186,37 @@ def test_small_and_root_leaf_hierarchies(ctx, orc, n_l, leaf):
     h.free()
 
 
+def test_keep_decisions_at_the_threshold(ctx, orc):
+    """s chosen so that p 2^32 lands within a few units of a pair's xi: the
+    fast reciprocal band must hand every such case to the exact division."""
+    import torch
+    tile = synth.dither_tile(100)
+    lights = np.array([[0.25, 0.0, 0.0], [0.0, 0.5, 0.0], [0.1, 0.2, 0.3]], np.float32)
+    eyes = np.zeros((1, 3), np.float32)
+    e_t = _eyes_t(ctx, eyes)
+    r0 = orc.eye_shift(tile, 0, 64)
+    for leaf in (1, 8):                      # internal node with leaf children / root leaf
+        h = ctx.build_hierarchy(lights, leaf_size=leaf)
+        ls = h.sorted_lights()
+        for i in range(3):
+            xi = orc.phi(i, r0, 32)
+            d = ls[i].astype(np.float32)
+            d2 = np.float32(np.float32(np.float32(d[0] * d[0]) + np.float32(d[1] * d[1]))
+                            + np.float32(d[2] * d[2]))
+            for delta in (-3.0, -1.0, -0.5, -1e-3, 0.0, 1e-3, 0.5, 1.0, 3.0):
+                p_target = (xi + delta) / 2.0 ** 32
+                if not (0.0 < p_target < 1.0):
+                    continue
+                s = float(np.float32(p_target * float(d2)))
+                for ds in (-1, 0, 1):           # neighbouring floats of s
+                    s2 = float(np.nextafter(np.float32(s), np.float32(np.inf if ds > 0 else -np.inf))) if ds else s
+                    pairs, n, _ = ctx.traverse_all(h, e_t, s2, 64)
+                    got = sorted(int(x) for x in pairs[:, 1].cpu().numpy())
+                    exp = [k for k in range(3) if orc.accept(eyes[0], ls[k], s2, orc.phi(k, r0, 32))]
+                    assert got == exp, (leaf, i, delta, ds, s2)
+        h.free()
+
+
 def test_coincident_lights_split_at_midpoint(ctx, orc):
     base = synth.uniform_points(40, 950)
     lights = np.repeat(base, 25, axis=0)            # 25 copies each: equal Morton codes
