@@ -29,8 +29,8 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # Algorithmic 32-bit VALU lane-operations per unit of traversal work, counted
-# from the arithmetic each unit needs as gfx950 executes it (the design doc lists
-# the count):
+# from the arithmetic each unit needs as gfx950 executes it (the breakdown
+# follows):
 #   visit : one internal node popped, both children bounded -- inherited
 #           minimum selection 5; per child 34 (box distance 9, squares and sum
 #           5, IEEE division 10, margin and min 3, fixed-point keep test 5,
@@ -214,8 +214,8 @@ def main():
     p.add_argument("--no-cpu-baseline", action="store_true")
     args = p.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design of the sharded path is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the sharded design is documented, not built)", file=sys.stderr)
         sys.exit(2)
     fn = frame_workload if args.workload == "frame" else rangemin_workload
     line = fn(args)

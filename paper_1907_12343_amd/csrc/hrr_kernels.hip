@@ -341,6 +341,10 @@ __device__ __forceinline__ void emit2(OutState& O, const ItemDesc& D, bool e0, u
     const uint64_t m0 = ballot(e0), m1 = ballot(e1);
     const uint32_t cnt = (uint32_t)(__popcll(m0) + __popcll(m1));
     if (cnt == 0) return;
+    if (D.capacity == 0) {   // counting launch: nothing is stored
+        O.count += cnt;
+        return;
+    }
     if (O.chunk == kNoChunk) {
         set_chunk<W>(O, D, alloc_chunk(D));
         O.fill = 0;
