@@ -44,6 +44,7 @@ OPS_RMQ = 40
 OPS_LEAF = 30
 OPS_PAIR = 6
 BYTES_PER_QUERY = 20   # range minimum: a, b, r in; argmin, min out
+RMQ_METHODS = {"paper": 0, "direct": 1, "paper_full": 2, "paper_loop": 3}
 
 
 def _sync_all():
@@ -64,7 +65,7 @@ def frame_workload(args):
     build_s = time.time() - t0
     eyes = torch.from_numpy(fr["eyes"]).to("cuda:0")
     n_eyes = fr["eyes"].shape[0]
-    method = hrr.RMQ_DIRECT if args.rmq == "direct" else hrr.RMQ_PAPER
+    method = RMQ_METHODS[args.rmq]
     kw = dict(rmq_method=method, eyes_per_wave=args.epw, stack_entries=args.stack)
     n = ctx.count(h, eyes, fr["s"], fr["width"], **kw)
     pairs = torch.empty((max(n, 1), 2), dtype=torch.int32, device="cuda:0")
@@ -121,17 +122,17 @@ def frame_workload(args):
                                  else (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0)},
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_frame(fr, h.permutation(), n_eyes, args)
+        line["cpu_baseline"] = cpu_baseline_frame(fr, n_eyes, args)
     h.free()
     ctx.close()
     return line
 
 
-def cpu_baseline_frame(fr, perm, n_eyes, args):
+def cpu_baseline_frame(fr, n_eyes, args):
     import numpy as np
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
-    ls = fr["lights"][perm]
+    ls = fr["lights"][oracle.morton_order(fr["lights"])]   # the oracle's own light order
     sel = np.linspace(0, n_eyes - 1, args.cpu_eyes).astype(np.uint32)
     t0 = time.perf_counter()
     oracle.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], ls, fr["s"], threads=threads)
@@ -153,7 +154,7 @@ def rangemin_workload(args):
     ta, tb, tr = (hrr.u32_tensor(x, dev) for x in (a, b, r))
     k = torch.empty_like(ta)
     v = torch.empty_like(ta)
-    method = hrr.RMQ_DIRECT if args.rmq == "direct" else hrr.RMQ_PAPER
+    method = RMQ_METHODS[args.rmq]
     for _ in range(args.warmup):
         ctx.range_min(ta, tb, tr, method=method, out_k=k, out_v=v)
     stream = torch.cuda.current_stream()
@@ -197,13 +198,240 @@ def rangemin_workload(args):
     return line
 
 
+def _ops_of(st, n_pairs):
+    multi_leaf_tests = max(st["leaf_tests"] - 2 * st["node_visits"], 0)
+    return (st["node_visits"] * OPS_VISIT + st["rmq_calls"] * OPS_RMQ
+            + multi_leaf_tests * OPS_LEAF + n_pairs * OPS_PAIR)
+
+
+def batched_workload(args):
+    """256 independent caches (own mixture, 2^U[10,20] lights, 2^U[10,16]
+    eyes, s = 1e-4) in ONE persistent launch, against 256 plain launches of
+    the same items on the same GPU.  The launch shape and the leaf size come
+    from the autotuner, run once on a mid-size cache before timing."""
+    import numpy as np
+    import torch
+    import paper_1907_12343_amd as hrr
+    import synth
+
+    ctx = hrr.Context(synth.dither_tile(100), device=0)
+    caches = [synth.batched_cache(c) for c in range(256)]
+    sizes = np.array([d["lights"].shape[0] for d in caches])
+    probe = caches[int(np.argsort(sizes)[len(sizes) // 2])]
+    t0 = time.time()
+    cand = [ctx.build_hierarchy(probe["lights"], leaf_size=L) for L in (1, 2, 4, 8)]
+    pe = torch.from_numpy(probe["eyes"]).to("cuda:0")
+    tuned = ctx.autotune(cand, pe, probe["s"], probe["width"], max_probe_eyes=8192)
+    for h in cand:
+        h.free()
+    leaf = tuned["leaf_size"]
+    hs = [ctx.build_hierarchy(d["lights"], leaf_size=leaf) for d in caches]
+    setup_s = time.time() - t0
+    eyes = [torch.from_numpy(d["eyes"]).to("cuda:0") for d in caches]
+    counts = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    total = int(offs[-1])
+    pairs = torch.empty((max(total, 1), 2), dtype=torch.int32, device="cuda:0")
+    items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=int(offs[k]),
+                  out_capacity=int(counts[k]))
+             for k, (h, e, d) in enumerate(zip(hs, eyes, caches))]
+    n_eyes = int(sum(d["eyes"].shape[0] for d in caches))
+    got, st = ctx.traverse_batched(items, pairs, stats=True)
+    assert [int(x) for x in got] == counts
+
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        _sync_all()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        _sync_all()
+        return (time.perf_counter() - t0) * 1e3 / args.steps, e0.elapsed_time(e1) / args.steps
+
+    ms, gpu_ms = timed(lambda: ctx.traverse_batched(items, pairs))
+
+    def plain():
+        for k, (h, e, d) in enumerate(zip(hs, eyes, caches)):
+            ctx.traverse(h, e, d["s"], d["width"], pairs=pairs[offs[k]:offs[k] + max(counts[k], 1)],
+                         capacity=counts[k])
+
+    ms_plain, _ = timed(plain)
+    ops = _ops_of(st, total)
+    achieved = ops / (gpu_ms * 1e-3) / 1e12
+    line = {
+        "metric": "eye-vertex traversals/s", "value": n_eyes / (ms * 1e-3), "unit": "eyes/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32",
+        "data": "synthetic",
+        "config": {"workload": "batched: 256 caches, own 64-Gaussian mixture each, 2^U[10,20] "
+                               "lights, 2^U[10,16] eyes, s=1e-4, one launch",
+                   "n_eyes": n_eyes, "n_lights": int(sizes.sum()), "leaf": leaf,
+                   "tuned": tuned, "parallelism": "1 GPU"},
+        "pairs_per_s": total / (ms * 1e-3), "accepted_pairs": total, "kernel_ms": gpu_ms,
+        "setup_s": setup_s,
+        "plain_launches": {"ms_per_step": ms_plain, "eyes_per_s": n_eyes / (ms_plain * 1e-3),
+                           "speedup_of_batched": ms_plain / ms},
+        "units": {k: st[k] for k in ("node_visits", "rmq_calls", "leaf_tests")},
+        "algorithmic_lane_ops": ops,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
+                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
+    }
+    for h in hs:
+        h.free()
+    ctx.close()
+    return line
+
+
+def served_workload(args):
+    """Serving loop: 16 resident hierarchies of 2^(16+6h/15) lights, requests
+    of 2^U[8,18] eyes (each with its own shift offset, s = 1e-4) arriving as
+    a Poisson stream at 0.3, 0.6 and 0.9 of the measured saturation rate.
+    Reports latency percentiles per load and compares with plain single
+    launches served one at a time (FIFO queue replayed over the measured
+    per-request service times of the plain path)."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_1907_12343_amd as hrr
+    import synth
+
+    ctx = hrr.Context(synth.dither_tile(100), device=0)
+    t0 = time.time()
+    scenes = [synth.served_hierarchy(k) for k in range(16)]
+    hs = [ctx.build_hierarchy(sc["lights"]) for sc in scenes]
+    n_req = args.requests
+    base = synth.served_requests(n_req, 1.0)
+    req_eyes = [synth.request_eyes(scenes[int(base["hier"][q])]["centers"], int(base["size"][q]),
+                                   int(base["eye_seed"][q])) for q in range(n_req)]
+    setup_s = time.time() - t0
+    s_val = 1e-4
+
+    def submit(q):
+        return ctx.submit(hs[int(base["hier"][q])], req_eyes[q], 64, int(base["offset"][q]), s_val)
+
+    ctx.server_start(hbm_budget_bytes=int(args.budget_gib * (1 << 30)), max_inflight=2,
+                     max_batch_eyes=1 << 20, max_batch_items=64, pairs_per_eye_guess=2000.0)
+
+    def drain(tickets, out):
+        for t in tickets:
+            while not ctx.wait(t, 60000):
+                pass
+            _, n, info = ctx.poll(t)
+            out.append((info["done_s"] - info["submit_s"], n, info["launches"]))
+            ctx.release(t)
+
+    # warm-up and saturation: everything submitted at once
+    warm = min(16, n_req)
+    res = []
+    drain([submit(q) for q in range(warm)], res)
+    t_sat = time.perf_counter()
+    res = []
+    drain([submit(q) for q in range(n_req)], res)
+    sat_s = time.perf_counter() - t_sat
+    sat_rate = n_req / sat_s
+    sat_eyes = float(base["size"].sum()) / sat_s
+    sat_pairs = sum(r[1] for r in res) / sat_s
+
+    # per load: about args.load_seconds of arrivals, at least 100 requests
+    def n_at(rate):
+        return int(min(n_req, max(100, rate * args.load_seconds)))
+
+    loads = {}
+    for load in (0.3, 0.6, 0.9):
+        rate = load * sat_rate
+        m = n_at(rate)
+        arr = synth.served_requests(n_req, rate)["t"][:m]
+        tickets = [None] * m
+        ready = threading.Semaphore(0)
+        out = []
+
+        def waiter():
+            for q in range(m):
+                ready.acquire()
+                drain([tickets[q]], out)
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        for q in range(m):
+            delay = start + arr[q] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[q] = submit(q)
+            ready.release()
+        th.join()
+        wall = time.perf_counter() - start
+        lat = np.array([r[0] for r in out]) * 1e3
+        loads["%.1f" % load] = {
+            "offered_req_per_s": rate, "requests": m, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "pairs_per_s": sum(r[1] for r in out) / wall,
+            "eyes_per_s": float(base["size"][:m].sum()) / wall,
+            "retried": int(sum(1 for r in out if r[2] > 1))}
+    stats = ctx.server_stats()
+    ctx.server_stop()
+
+    # plain single launches: upload, count, traverse, one request at a time
+    service = np.zeros(n_req)
+    for q in range(n_req):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        e = torch.from_numpy(req_eyes[q]).to("cuda:0")
+        ctx.traverse_all(hs[int(base["hier"][q])], e, s_val, 64, shift_offset=int(base["offset"][q]))
+        torch.cuda.synchronize()
+        service[q] = time.perf_counter() - t1
+    plain = {"req_per_s": n_req / service.sum(), "eyes_per_s": float(base["size"].sum()) / service.sum()}
+    for load in (0.3, 0.6, 0.9):
+        m = n_at(load * sat_rate)
+        arr = synth.served_requests(n_req, load * sat_rate)["t"][:m]
+        free_at, lat = 0.0, []
+        for q in range(m):
+            begin = max(arr[q], free_at)
+            free_at = begin + service[q]
+            lat.append((free_at - arr[q]) * 1e3)
+        lat = np.array(lat)
+        plain["load_%.1f" % load] = {"p50_ms": float(np.percentile(lat, 50)),
+                                     "p99_ms": float(np.percentile(lat, 99)),
+                                     "stable": bool(service[:m].sum() < arr[-1] + service[m - 1])}
+    line = {
+        "metric": "eye-vertex traversals/s", "value": loads["0.9"]["eyes_per_s"], "unit": "eyes/s",
+        "n_gpus": 1, "steps": n_req, "warmup": warm, "ms_per_step": None,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32",
+        "data": "synthetic",
+        "config": {"workload": "served: 16 resident hierarchies 2^(16+6h/15) lights, Poisson "
+                               "requests of 2^U[8,18] eyes, own shift offset, s=1e-4",
+                   "requests": n_req, "budget_gib": args.budget_gib, "parallelism": "1 GPU"},
+        "saturation": {"req_per_s": sat_rate, "eyes_per_s": sat_eyes, "pairs_per_s": sat_pairs},
+        "loads": loads, "plain_single_launches": plain,
+        "server_stats": stats, "setup_s": setup_s, "roofline": None,
+    }
+    for h in hs:
+        h.free()
+    ctx.close()
+    return line
+
+
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="frame", choices=["frame", "rangemin"])
-    p.add_argument("--rmq", default="paper", choices=["paper", "direct"])
+    p.add_argument("--workload", default="frame",
+                   choices=["frame", "rangemin", "batched", "served"])
+    p.add_argument("--requests", type=int, default=300, help="served: requests per load")
+    p.add_argument("--budget-gib", type=float, default=64.0, help="served: device arena")
+    p.add_argument("--load-seconds", type=float, default=10.0,
+                   help="served: seconds of arrivals per offered load")
+    p.add_argument("--rmq", default="paper", choices=list(RMQ_METHODS),
+                   help="range-minimum method: paper (bit-parallel flip-position selection, "
+                        "default), direct, paper_full (sweeps as loops), paper_loop (pruned loops)")
     p.add_argument("--epw", type=int, default=1)
     p.add_argument("--stack", type=int, default=512)
     p.add_argument("--traffic-kib", type=float, nargs=2, default=None,
@@ -217,7 +445,8 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sharded design is documented, not built)", file=sys.stderr)
         sys.exit(2)
-    fn = frame_workload if args.workload == "frame" else rangemin_workload
+    fn = {"frame": frame_workload, "rangemin": rangemin_workload,
+          "batched": batched_workload, "served": served_workload}[args.workload]
     line = fn(args)
     print(json.dumps(line), flush=True)
 

@@ -41,8 +41,9 @@
  * hrr_last_error() returns a message for the last failing call on that
  * context (thread-local to the calling thread).
  *
- * Threads.  hrr_submit / hrr_poll / hrr_wait / hrr_cancel / hrr_release and
- * the server statistics call are thread-safe.  All other calls on one context
+ * Threads.  hrr_submit / hrr_poll / hrr_wait / hrr_result_copy / hrr_cancel /
+ * hrr_release and the server statistics call are thread-safe (also against
+ * the server's own workers).  All other calls on one context
  * must not run concurrently.
  */
 #ifndef HRR_H
@@ -251,51 +252,95 @@ uint32_t hrr_tuned_leaf_size(const hrr_ctx* ctx, uint32_t n_lights);
 /* ------------------------------------------------------------------------- */
 /* Serving: resident hierarchies, continuous batching of eye tiles            */
 /* ------------------------------------------------------------------------- */
+/*
+ * A request is one eye tile (a few hundred to a few hundred thousand eyes)
+ * against one hierarchy already resident on the GPU, with its own additive
+ * shift offset folded into every r_j (Section 3: an extra rotation is
+ * absorbed into the shift) and its own s.  Its result is exactly what
+ * hrr_traverse would return for the same eyes, hierarchy, width, offset and
+ * s (same set of pairs; order unspecified).
+ *
+ * The server owns one device arena of hbm_budget_bytes, allocated at start,
+ * that holds the eyes of running requests and the pairs of finished ones
+ * until they are released.  max_inflight worker threads (one HIP stream
+ * each) repeatedly take as many queued requests as fit (FIFO; up to
+ * max_batch_items requests and max_batch_eyes eyes, and as much arena as is
+ * free) and run them as the items of ONE persistent traversal launch; while
+ * one launch runs, newly arrived requests are batched into the next.  Each
+ * request reserves output space from a running estimate of pairs per eye for
+ * its hierarchy; a request whose count exceeds its reservation is re-run once
+ * with the exact count reserved (hrr_ticket_info.launches > 1).
+ *
+ * Lifetime: a hierarchy must stay alive while requests on it are queued or
+ * running.  Results hold arena space until hrr_release; a client that never
+ * releases eventually blocks admission of further requests.  hrr_server_stop
+ * (and hrr_destroy) invalidate every ticket and every result address.
+ */
 
 typedef struct hrr_server_config {
-    uint64_t hbm_budget_bytes;   /* device memory for request eyes + results */
-    uint32_t max_inflight;       /* launches in flight at once (one stream each), 1..8 */
-    uint32_t max_batch_eyes;     /* eyes per launch before a batch is closed */
-    uint32_t max_batch_items;    /* requests per launch */
-    uint32_t eyes_per_wave;      /* 0 = autotuned */
-    float pairs_per_eye_guess;   /* initial output reservation per eye (adapted online) */
+    uint64_t hbm_budget_bytes;   /* device arena for request eyes + results (>= 1 MiB) */
+    uint32_t max_inflight;       /* launches in flight at once (one worker + stream each), 1..8 */
+    uint32_t max_batch_eyes;     /* eyes per launch before a batch is closed (>= 1) */
+    uint32_t max_batch_items;    /* requests per launch, 1..1024 */
+    uint32_t eyes_per_wave;      /* 0 = tuned / default by hierarchy size; else 1, 2, 4 or 8 */
+    float pairs_per_eye_guess;   /* output reservation per eye before any request on a
+                                    hierarchy has finished (> 0; adapted online) */
 } hrr_server_config;
 
 typedef struct hrr_server_stats {
     uint64_t submitted, completed, cancelled, rejected, launches, retries;
-    uint64_t pairs;
+    uint64_t pairs;                 /* pairs of completed requests */
     double p50_ms, p99_ms, mean_ms; /* submit -> complete latency of completed requests */
     double busy_s;                  /* wall time with at least one launch in flight */
-    uint64_t peak_bytes;            /* high-water mark of the budget in use */
+    uint64_t peak_bytes;            /* high-water mark of the arena in use */
 } hrr_server_stats;
 
 typedef struct hrr_ticket_info {
-    double submit_s, start_s, done_s;  /* host monotonic clock, seconds */
+    double submit_s, start_s, done_s;  /* host monotonic clock (seconds): submit, first
+                                          launch enqueued, result complete */
     uint64_t n_pairs;
     uint32_t launches;                 /* > 1 if the request was re-run after an output overflow */
 } hrr_ticket_info;
 
-/* Start the serving loop (host threads).  The budget is allocated once. */
+/* Start the serving workers and allocate the arena.  HRR_E_BUSY if a server
+ * already runs on ctx, HRR_E_INVALID for a bad config, HRR_E_NOMEM if the
+ * arena cannot be allocated. */
 hrr_status hrr_server_start(hrr_ctx* ctx, const hrr_server_config* cfg);
-/* Stop: waits for in-flight launches, cancels queued requests. */
+/* Stop: queued requests are cancelled, running launches finish, then the
+ * workers exit and the arena is freed.  HRR_OK also if no server runs. */
 hrr_status hrr_server_stop(hrr_ctx* ctx);
-/* Queue a request: an eye tile (host xyz, 3*n_eyes fp32, copied) against a
- * resident hierarchy, with its own shift offset and s.  Returns a ticket.
- * HRR_E_NOMEM if the tile could never fit the budget, HRR_E_BUSY if the
- * server is not running. */
+/* Queue a request.  eyes_xyz: host, 3*n_eyes fp32, copied before the call
+ * returns (finite values only).  width: pixels per row of the tile, as in
+ * hrr_eyes.  shift_offset: added to every r_j mod 2^32.  s: finite, > 0.
+ * *ticket (host) receives an id unique within this server.  HRR_E_NOMEM (and
+ * the request counted as rejected) if the tile could never fit the arena,
+ * HRR_E_BUSY if no server runs, HRR_E_INVALID for bad arguments. */
 hrr_status hrr_submit(hrr_ctx* ctx, const hrr_hierarchy* h, const float* eyes_xyz,
                       uint32_t n_eyes, uint32_t width, uint32_t shift_offset,
                       float s, uint64_t* ticket);
-/* HRR_E_NOTREADY until the request is complete; then HRR_OK with the device
- * address of its (j, i) pairs (valid until hrr_release) and the count. */
+/* HRR_E_NOTREADY while queued or running.  When complete: HRR_OK, *pairs_dev
+ * (host variable) = device address of the request's n_pairs (j, i) u32 pairs
+ * inside the arena (NULL if none; valid until hrr_release), *n_pairs = their
+ * count.  HRR_E_CANCELLED for a cancelled request; the failing status (with
+ * hrr_last_error set) for one that failed; HRR_E_INVALID for an unknown ticket.
+ * pairs_dev, n_pairs and info may each be NULL. */
 hrr_status hrr_poll(hrr_ctx* ctx, uint64_t ticket, const uint32_t** pairs_dev,
                     uint64_t* n_pairs, hrr_ticket_info* info);
-/* Block until complete or timeout_ms elapses (HRR_E_NOTREADY). */
+/* Block until the request is no longer queued or running, or timeout_ms
+ * elapses (then HRR_E_NOTREADY).  Returns what hrr_poll would. */
 hrr_status hrr_wait(hrr_ctx* ctx, uint64_t ticket, uint32_t timeout_ms);
-/* Cancel a request that has not started; HRR_E_BUSY if it already runs. */
+/* Copy a complete request's pairs to dst (device, 2*capacity u32) on
+ * `stream` and wait for the copy.  HRR_E_OVERFLOW (first capacity pairs
+ * copied) if capacity is smaller than the count; other statuses as hrr_poll. */
+hrr_status hrr_result_copy(hrr_ctx* ctx, uint64_t ticket, uint32_t* dst, uint64_t capacity,
+                           void* stream);
+/* Cancel a queued request (HRR_OK).  HRR_E_BUSY if it is already running or
+ * complete, HRR_E_INVALID for an unknown ticket. */
 hrr_status hrr_cancel(hrr_ctx* ctx, uint64_t ticket);
-/* Free a completed or cancelled request's result memory. */
+/* Forget a complete, failed or cancelled request and free its result
+ * memory.  HRR_E_BUSY while it is queued or running. */
 hrr_status hrr_release(hrr_ctx* ctx, uint64_t ticket);
+/* Counters since hrr_server_start.  HRR_E_BUSY if no server runs. */
 hrr_status hrr_server_get_stats(hrr_ctx* ctx, hrr_server_stats* out);
 
 #ifdef __cplusplus

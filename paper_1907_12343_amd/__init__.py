@@ -107,6 +107,7 @@ SIGNATURES = {
     "hrr_submit": (_i32, [_P, _P, _P, _u32, _u32, _u32, _f32, _P]),
     "hrr_poll": (_i32, [_P, _u64, _P, _P, _P]),
     "hrr_wait": (_i32, [_P, _u64, _u32]),
+    "hrr_result_copy": (_i32, [_P, _u64, _P, _u64, _P]),
     "hrr_cancel": (_i32, [_P, _u64]),
     "hrr_release": (_i32, [_P, _u64]),
     "hrr_server_get_stats": (_i32, [_P, _P]),
@@ -315,8 +316,10 @@ class Context:
                                  _dptr(pairs), _dptr(weights), capacity, ctypes.byref(n),
                                  ctypes.byref(st), _stream_handle(stream))
         if code == HRR_E_OVERFLOW:
-            raise OverflowResult(code, "hrr_traverse: %d pairs exceed capacity %d"
+            err = OverflowResult(code, "hrr_traverse: %d pairs exceed capacity %d"
                                  % (n.value, capacity))
+            err.count = int(n.value)
+            raise err
         _check(code, "hrr_traverse")
         k = int(n.value)
         out = (pairs[:k], k, st.as_dict())
@@ -362,7 +365,9 @@ class Context:
                                          counts.ctypes.data_as(_P), ctypes.byref(st),
                                          _stream_handle(stream))
         if code == HRR_E_OVERFLOW:
-            raise OverflowResult(code, "hrr_traverse_batched: an item exceeded its capacity")
+            err = OverflowResult(code, "hrr_traverse_batched: an item exceeded its capacity")
+            err.counts = counts       # true count of every item
+            raise err
         _check(code, "hrr_traverse_batched")
         return counts, st.as_dict()
 
@@ -426,22 +431,20 @@ class Context:
     def release(self, ticket: int):
         _check(_lib.hrr_release(self.handle, ticket), "hrr_release")
 
+    def result(self, ticket: int, device=None, stream=None):
+        """Copy a complete request's pairs into a new (n, 2) int32 cuda tensor."""
+        import torch
+        ready = self.poll(ticket)
+        if ready is None:
+            raise HrrError(HRR_E_NOTREADY, "request %d has not finished" % ticket)
+        n = ready[1]
+        dev = torch.device("cuda", self.device) if device is None else device
+        out = torch.empty((max(n, 1), 2), dtype=torch.int32, device=dev)
+        _check(_lib.hrr_result_copy(self.handle, ticket, _dptr(out), n, _stream_handle(stream)),
+               "hrr_result_copy")
+        return out[:n]
+
     def server_stats(self):
         st = HrrServerStats()
         _check(_lib.hrr_server_get_stats(self.handle, ctypes.byref(st)), "hrr_server_get_stats")
         return st.as_dict()
-
-
-def pairs_from_device(addr: int, n: int, device):
-    """Copy n (j, i) pairs from a library-owned device address into a tensor."""
-    import torch
-    out = torch.empty((n, 2), dtype=torch.int32, device=device)
-    if n:
-        hip = ctypes.CDLL("libamdhip64.so.7")
-        hip.hipMemcpy.restype = ctypes.c_int
-        hip.hipMemcpy.argtypes = [_P, _P, ctypes.c_size_t, ctypes.c_int]
-        torch.cuda.synchronize()
-        rc = hip.hipMemcpy(_P(out.data_ptr()), _P(addr), n * 8, 3)   # device to device
-        if rc != 0:
-            raise HrrError(HRR_E_DEVICE, "hipMemcpy failed (%d)" % rc)
-    return out

@@ -351,6 +351,8 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
         return fail(HRR_E_DEVICE, "traversal kernel exhausted its stack spill region");
     if (S.error & ERR_PARTIALS_OVERFLOW)
         return fail(HRR_E_DEVICE, "traversal kernel exhausted its partial-chunk list");
+    if (S.error & ERR_UNFILLED)
+        return fail(HRR_E_DEVICE, "output compaction left positions below the count unfilled");
     if (S.error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", S.error);
     if (overflow) return fail(HRR_E_OVERFLOW, "output capacity exceeded");
     return HRR_OK;

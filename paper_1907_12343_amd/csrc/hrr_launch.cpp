@@ -83,22 +83,32 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     std::vector<ItemMeta>& M = S.meta;
     M.assign(n, ItemMeta{});
     unsigned long long slack_total = 0, partial_total = 0;
+    // A wave walks the queues in the cyclic order q0, q0+1, ..., q0-1 and the
+    // tasks of each queue in increasing order, so the items it meets are
+    // nondecreasing except at the one wrap from the last queue to the first:
+    // it leaves an item (and publishes a partly filled chunk) at most twice,
+    // and at most once in a one-item launch.  Every allocated chunk other
+    // than those is full, so the pairs stored past the capacity (slack) and
+    // the holes below it are bounded by partial_cap chunks each; a slack of
+    // twice that lets the compaction fill every hole below min(count, capacity).
+    const uint64_t leaves_per_wave = n > 1 ? 2 : 1;
     for (size_t k = 0; k < n; ++k) {
         const uint64_t wk = std::max<uint64_t>(1, std::min<uint64_t>(waves, tasks_of[k]));
+        const uint64_t pk = std::max<uint64_t>(1, std::min<uint64_t>(leaves_per_wave * waves, tasks_of[k]));
         const unsigned long long capk = items[k].out_capacity;
-        // about four chunks per touching wave, 64..8192 pairs
+        // about sixteen chunks per touching wave, 128..8192 pairs
         uint32_t shift = kMinChunkShift;
-        while (shift < kMaxChunkShift && (capk >> (shift + 1)) >= 4 * wk) ++shift;
+        while (shift < kMaxChunkShift && (capk >> (shift + 1)) >= 16 * wk) ++shift;
         ItemMeta& m = M[k];
         m.out_offset = items[k].out_offset;
         m.capacity = capk;
         m.chunk_shift = shift;
-        m.slack = capk ? 2ull * wk << shift : 0ull;
+        m.slack = capk ? 2ull * pk << shift : 0ull;
         m.slack_off = slack_total;
         slack_total += m.slack;
-        m.partial_cap = (uint32_t)wk;
+        m.partial_cap = (uint32_t)pk;
         m.partial_off = partial_total;
-        partial_total += wk;
+        partial_total += pk;
     }
 
     // ---- eye processing order: counting sort by (item, Morton cell) ----
@@ -305,8 +315,9 @@ hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weig
         if (P) {
             S.h_partials.resize(2 * P);
             const unsigned long long* src = static_cast<const unsigned long long*>(S.partials.p) + 2 * m.partial_off;
-            if ((e = hipMemcpy(S.h_partials.data(), src, 2 * P * sizeof(unsigned long long), hipMemcpyDeviceToHost)) !=
-                hipSuccess)
+            if ((e = hipMemcpyAsync(S.h_partials.data(), src, 2 * P * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(stream)) != hipSuccess)
                 return hip_fail(e, "read partial chunks");
             for (unsigned long long q = 0; q < P; ++q) part[q] = {S.h_partials[2 * q], S.h_partials[2 * q + 1]};
             std::sort(part.begin(), part.end());
@@ -325,7 +336,11 @@ hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weig
             const unsigned long long fill = (pi < part.size() && part[pi].first == c) ? part[pi].second : C;
             const unsigned long long lo = std::max(c * C, target);
             const unsigned long long hi = std::min(c * C + fill, limit);
-            if (lo < hi) data.push_back({lo, hi});
+            // positions below the capacity are in the caller's slice, the
+            // rest in the slack area: a chunk that straddles the capacity
+            // gives two segments
+            if (lo < std::min(hi, cap)) data.push_back({lo, std::min(hi, cap)});
+            if (std::max(lo, cap) < hi) data.push_back({std::max(lo, cap), hi});
         }
         unsigned long long unfilled = 0;
         size_t hi_ = 0, di = 0;
@@ -348,14 +363,14 @@ hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weig
             if (dpos == data[di].second && ++di < data.size()) dpos = data[di].first;
         }
         S.stored[k] = target - unfilled;
+        if (unfilled) S.error |= ERR_UNFILLED;   // pairs lost: never expected
     }
     const size_t n_seg = S.h_segments.size() / 3;
     if (n_seg) {
         if ((e = S.segments.ensure(S.h_segments.size() * sizeof(unsigned long long))) != hipSuccess)
             return hip_fail(e, "segments");
-        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "before hole filling");
-        if ((e = hipMemcpy(S.segments.p, S.h_segments.data(), S.h_segments.size() * sizeof(unsigned long long),
-                           hipMemcpyHostToDevice)) != hipSuccess)
+        if ((e = hipMemcpyAsync(S.segments.p, S.h_segments.data(), S.h_segments.size() * sizeof(unsigned long long),
+                                hipMemcpyHostToDevice, stream)) != hipSuccess)
             return hip_fail(e, "upload segments");
         if ((e = hrr_launch_move_pairs(static_cast<const unsigned long long*>(S.segments.p), (uint32_t)n_seg, pairs,
                                        weights, static_cast<const uint32_t*>(S.slack_pairs.p),

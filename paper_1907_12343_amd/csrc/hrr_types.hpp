@@ -95,6 +95,7 @@ constexpr uint32_t kMaxNodes = 1u << kSlotShift;
 
 enum StatIdx { ST_EYES = 0, ST_PAIRS, ST_VISITS, ST_RMQ, ST_LEAF, ST_SPILLS, ST_MAXSTACK, ST_N };
 
-enum ErrCode { ERR_NONE = 0, ERR_SPILL_OVERFLOW = 1, ERR_PARTIALS_OVERFLOW = 2 };
+// Kernel-reported (1, 2) and host-detected (4) internal failures.
+enum ErrCode { ERR_NONE = 0, ERR_SPILL_OVERFLOW = 1, ERR_PARTIALS_OVERFLOW = 2, ERR_UNFILLED = 4 };
 
 }  // namespace hrr

@@ -152,3 +152,148 @@ def test_host_builder_matches_oracle_order_and_is_valid(orc, build_harness, n, l
 
     assert walk(0, 0, n, 0) == depth
     assert len(seen) == len(nodes)
+
+
+ARENA_HARNESS = r"""
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include "hrr_arena.hpp"
+// stdin: size, then ops "a id bytes" | "f id" | "s id bytes"; stdout: one line per op
+int main() {
+    unsigned long long size;
+    if (scanf("%llu", &size) != 1) return 2;
+    hrr::Arena A;
+    A.init(size);
+    std::map<long, std::pair<unsigned long long, unsigned long long>> blocks;
+    char op[4];
+    long id;
+    unsigned long long bytes;
+    while (scanf("%3s %ld", op, &id) == 2) {
+        if (op[0] == 'a' || op[0] == 's') {
+            if (scanf("%llu", &bytes) != 1) return 3;
+        }
+        if (op[0] == 'a') {
+            uint64_t off = 0;
+            if (A.alloc(bytes, &off)) {
+                blocks[id] = {off, bytes};
+                printf("%llu\n", (unsigned long long)off);
+            } else {
+                printf("-1\n");
+            }
+        } else if (op[0] == 'f') {
+            A.release(blocks[id].first, blocks[id].second);
+            blocks.erase(id);
+            printf("ok\n");
+        } else {
+            A.shrink(blocks[id].first, blocks[id].second, bytes);
+            blocks[id].second = bytes;
+            printf("ok\n");
+        }
+    }
+    printf("%llu %llu %llu %zu\n", (unsigned long long)A.used(), (unsigned long long)A.peak(),
+           (unsigned long long)A.largest_free(), A.free_blocks());
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def arena_harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("arena")
+    src = d / "arena.cpp"
+    src.write_text(ARENA_HARNESS)
+    exe = d / "arena"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+class _UnitModel:
+    """First fit over a bitmap of 256-byte units: the lowest run of free units."""
+
+    def __init__(self, size):
+        self.units = [False] * (size // 256)
+        self.peak = 0
+
+    @staticmethod
+    def n_units(b):
+        return max(1, (b + 255) // 256)
+
+    def alloc(self, b):
+        k = self.n_units(b)
+        run = 0
+        for u, used in enumerate(self.units):
+            run = 0 if used else run + 1
+            if run == k:
+                start = u - k + 1
+                for v in range(start, u + 1):
+                    self.units[v] = True
+                self.peak = max(self.peak, sum(self.units))
+                return start * 256
+        return -1
+
+    def free(self, off, b):
+        for v in range(off // 256, off // 256 + self.n_units(b)):
+            assert self.units[v]
+            self.units[v] = False
+
+    def largest(self):
+        best = run = 0
+        for used in self.units:
+            run = 0 if used else run + 1
+            best = max(best, run)
+        return best * 256
+
+    def blocks(self):
+        n, prev = 0, True
+        for used in self.units:
+            if not used and prev:
+                n += 1
+            prev = used
+        return n
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_server_arena_is_first_fit_and_coalesces(arena_harness, seed):
+    rng = np.random.default_rng(900 + seed)
+    size = 256 * 400 + (seed * 37)      # a size that is not a multiple of 256 on purpose
+    model = _UnitModel(size)
+    live = {}
+    ops, expect = ["%d" % size], []
+    nid = 0
+    for _ in range(600):
+        u = rng.random()
+        if u < 0.5 or not live:
+            b = int(rng.integers(0, 256 * 24))
+            off = model.alloc(b)
+            ops.append("a %d %d" % (nid, b))
+            expect.append(str(off))
+            if off >= 0:
+                live[nid] = (off, b)
+            nid += 1
+        elif u < 0.85:
+            k = list(live)[int(rng.integers(len(live)))]
+            off, b = live.pop(k)
+            model.free(off, b)
+            ops.append("f %d" % k)
+            expect.append("ok")
+        else:
+            k = list(live)[int(rng.integers(len(live)))]
+            off, b = live[k]
+            nb = int(rng.integers(0, b + 1))
+            keep = model.n_units(nb)
+            model.free(off + keep * 256, b - keep * 256) if model.n_units(b) > keep else None
+            live[k] = (off, nb)
+            ops.append("s %d %d" % (k, nb))
+            expect.append("ok")
+    # free everything: one block of the whole (rounded-down) size remains
+    for k, (off, b) in list(live.items()):
+        model.free(off, b)
+        ops.append("f %d" % k)
+        expect.append("ok")
+    out = subprocess.run([arena_harness], input="\n".join(ops) + "\n", capture_output=True,
+                         text=True, check=True).stdout.split("\n")
+    assert out[:len(expect)] == expect
+    used, peak, largest, nblocks = map(int, out[len(expect)].split())
+    assert used == 0 and nblocks == 1 and largest == size // 256 * 256
+    assert peak == model.peak * 256

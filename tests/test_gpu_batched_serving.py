@@ -1,0 +1,397 @@
+"""GPU tests of the batched launch, the autotuner and the serving loop.
+
+Every item of a batched launch, and every served request, must return the
+same pair set as a plain hrr_traverse of that item alone, which in turn must
+equal the all-pairs oracle (checked here on sampled eyes of each item).
+"""
+import threading
+
+import numpy as np
+import pytest
+
+import synth
+from _helpers import pair_keys_from_gpu, pair_keys_from_oracle, select_pairs_of_eyes
+
+pytestmark = pytest.mark.gpu
+
+TILE_SEED = 100
+
+
+@pytest.fixture(scope="module")
+def hrr():
+    import paper_1907_12343_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(hrr):
+    c = hrr.Context(synth.dither_tile(TILE_SEED))
+    yield c
+    c.close()
+
+
+def _dev(ctx, a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(ctx.torch_device)
+
+
+def _oracle_keys(orc, lights, eyes, sel, width, offset, s):
+    ls = lights[orc.morton_order(lights)]
+    out = orc.accept_eyes(eyes, sel, width, offset, synth.dither_tile(TILE_SEED), ls, s,
+                          lists=True)
+    return pair_keys_from_oracle(out, sel)
+
+
+def _plain_keys(ctx, h, eyes_t, s, width, offset=0):
+    pairs, n, _ = ctx.traverse_all(h, eyes_t, s, width, shift_offset=offset)
+    return pair_keys_from_gpu(pairs)
+
+
+def _small_cache(c, max_lights=1 << 16, max_eyes=1 << 12):
+    """Cache c of the batched workload, cut to sizes the oracle samples fast."""
+    d = synth.batched_cache(c)
+    return dict(lights=d["lights"][:max_lights], eyes=d["eyes"][:max_eyes], width=d["width"],
+                s=d["s"])
+
+
+# ---------------------------------------------------------------------------
+# batched launch
+# ---------------------------------------------------------------------------
+
+def test_batched_items_equal_plain_and_oracle(ctx, orc):
+    import torch
+    caches = [_small_cache(c) for c in range(10)]
+    hs = [ctx.build_hierarchy(d["lights"]) for d in caches]
+    eyes = [_dev(ctx, d["eyes"]) for d in caches]
+    counts = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    pairs = torch.empty((max(int(offs[-1]), 1), 2), dtype=torch.int32, device=ctx.torch_device)
+    items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=int(offs[k]),
+                  out_capacity=int(counts[k]))
+             for k, (h, e, d) in enumerate(zip(hs, eyes, caches))]
+    got, st = ctx.traverse_batched(items, pairs)
+    assert [int(x) for x in got] == counts
+    rng = np.random.default_rng(7)
+    for k, d in enumerate(caches):
+        sl = pairs[offs[k]:offs[k + 1]]
+        keys = pair_keys_from_gpu(sl)
+        assert np.array_equal(keys, _plain_keys(ctx, hs[k], eyes[k], d["s"], d["width"]))
+        sel = np.sort(rng.choice(d["eyes"].shape[0], 12, replace=False)).astype(np.uint32)
+        want = _oracle_keys(orc, d["lights"], d["eyes"], sel, d["width"], 0, d["s"])
+        assert np.array_equal(select_pairs_of_eyes(sl, sel), want)
+    for h in hs:
+        h.free()
+
+
+def test_batched_overflow_is_per_item(ctx, hrr):
+    import torch
+    caches = [_small_cache(c, 1 << 12, 1 << 10) for c in range(3)]
+    hs = [ctx.build_hierarchy(d["lights"]) for d in caches]
+    eyes = [_dev(ctx, d["eyes"]) for d in caches]
+    counts = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
+    assert min(counts) > 10
+    caps = [counts[0], counts[1] // 3, counts[2]]
+    offs = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
+    pairs = torch.full((int(offs[-1]), 2), -1, dtype=torch.int32, device=ctx.torch_device)
+    items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=int(offs[k]),
+                  out_capacity=int(caps[k]))
+             for k, (h, e, d) in enumerate(zip(hs, eyes, caches))]
+    with pytest.raises(hrr.OverflowResult) as ei:
+        ctx.traverse_batched(items, pairs)
+    assert [int(x) for x in ei.value.counts] == counts
+    for k in (0, 2):   # items within capacity are complete
+        keys = pair_keys_from_gpu(pairs[offs[k]:offs[k + 1]])
+        assert np.array_equal(keys, _plain_keys(ctx, hs[k], eyes[k], caches[k]["s"], 64))
+    # the overflowing item's slice holds distinct pairs of its true set
+    part = pair_keys_from_gpu(pairs[offs[1]:offs[2]])
+    full = _plain_keys(ctx, hs[1], eyes[1], caches[1]["s"], 64)
+    assert part.size == caps[1] and np.unique(part).size == part.size
+    assert np.isin(part, full).all()
+    for h in hs:
+        h.free()
+
+
+def test_batched_with_empty_items(ctx):
+    import torch
+    d = _small_cache(3, 1 << 12, 1 << 10)
+    h = ctx.build_hierarchy(d["lights"])
+    h0 = ctx.build_hierarchy(np.zeros((0, 3), np.float32))
+    e = _dev(ctx, d["eyes"])
+    e0 = torch.zeros((0, 3), dtype=torch.float32, device=ctx.torch_device)
+    n = ctx.count(h, e, d["s"], 64)
+    pairs = torch.empty((2 * n + 1, 2), dtype=torch.int32, device=ctx.torch_device)
+    items = [dict(h=h, eyes=e0, s=d["s"], width=64, out_offset=0, out_capacity=0),
+             dict(h=h, eyes=e, s=d["s"], width=64, out_offset=0, out_capacity=n),
+             dict(h=h0, eyes=e, s=d["s"], width=64, out_offset=n, out_capacity=1),
+             dict(h=h, eyes=e, s=d["s"], width=64, shift_offset=12345, out_offset=n + 1,
+                  out_capacity=n)]
+    ctx_counts, _ = ctx.traverse_batched(items, pairs)
+    assert int(ctx_counts[0]) == 0 and int(ctx_counts[1]) == n and int(ctx_counts[2]) == 0
+    assert np.array_equal(pair_keys_from_gpu(pairs[:n]), _plain_keys(ctx, h, e, d["s"], 64))
+    m = int(ctx_counts[3])
+    assert m <= n
+    assert np.array_equal(pair_keys_from_gpu(pairs[n + 1:n + 1 + m]),
+                          _plain_keys(ctx, h, e, d["s"], 64, offset=12345))
+    h.free()
+    h0.free()
+
+
+def test_batched_256_caches_counts_match_plain(ctx):
+    """The 256-cache workload at its real sizes: per-item counts of one
+    counting launch equal those of 256 plain launches."""
+    caches = [synth.batched_cache(c) for c in range(256)]
+    hs = [ctx.build_hierarchy(d["lights"]) for d in caches]
+    eyes = [_dev(ctx, d["eyes"]) for d in caches]
+    items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=0, out_capacity=0)
+             for h, e, d in zip(hs, eyes, caches)]
+    import paper_1907_12343_amd as hrr
+    with pytest.raises(hrr.OverflowResult) as ei:
+        ctx.traverse_batched(items, None)
+    got = [int(x) for x in ei.value.counts]
+    want = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
+    assert got == want
+    for h in hs:
+        h.free()
+
+
+# ---------------------------------------------------------------------------
+# autotuner
+# ---------------------------------------------------------------------------
+
+def test_autotune_choice_is_valid_and_results_unchanged(hrr):
+    ctx = hrr.Context(synth.dither_tile(TILE_SEED))
+    try:
+        d = _small_cache(5, 1 << 15, 1 << 13)
+        hs = [ctx.build_hierarchy(d["lights"], leaf_size=L) for L in (1, 2, 4, 8)]
+        e = _dev(ctx, d["eyes"])
+        best = ctx.autotune(hs, e, d["s"], d["width"], max_probe_eyes=4096)
+        assert best["eyes_per_wave"] in (1, 2, 4, 8)
+        assert best["stack_entries"] in (256, 512, 1024)
+        assert best["leaf_size"] in (1, 2, 4, 8)
+        assert best["ms"] > 0
+        assert ctx.tuned_leaf_size(d["lights"].shape[0]) == best["leaf_size"]
+        ref = _plain_keys(ctx, hs[0], e, d["s"], d["width"])
+        for h in hs:   # tuned shape (eyes_per_wave = stack_entries = 0) on every leaf size
+            pairs, n, _ = ctx.traverse_all(h, e, d["s"], d["width"], eyes_per_wave=0,
+                                           stack_entries=0)
+            assert np.array_equal(pair_keys_from_gpu(pairs), ref)
+        for h in hs:
+            h.free()
+    finally:
+        ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# serving loop
+# ---------------------------------------------------------------------------
+
+def _served_setup(ctx, sizes=(1 << 12, 1 << 14, 1 << 16)):
+    scenes = []
+    for k, n in enumerate(sizes):
+        rng = np.random.default_rng(700 + k)
+        centers = rng.random((64, 3))
+        lights = synth.mixture_points(n, centers, 710 + k)
+        scenes.append(dict(lights=lights, centers=centers, h=ctx.build_hierarchy(lights)))
+    return scenes
+
+
+def _requests(scenes, n_req, seed, lo=6.0, hi=11.0):
+    rng = np.random.default_rng(seed)
+    out = []
+    for q in range(n_req):
+        k = int(rng.integers(len(scenes)))
+        n = int(np.floor(2.0 ** rng.uniform(lo, hi)))
+        eyes = synth.request_eyes(scenes[k]["centers"], n, int(rng.integers(1 << 31)))
+        out.append(dict(scene=k, eyes=eyes, offset=int(rng.integers(0, 1 << 32)), width=64,
+                        s=1e-4))
+    return out
+
+
+def test_served_requests_equal_plain_and_oracle(ctx, orc):
+    scenes = _served_setup(ctx)
+    reqs = _requests(scenes, 48, 720)
+    ctx.server_start(hbm_budget_bytes=1 << 30, max_inflight=2, max_batch_items=16,
+                     pairs_per_eye_guess=64.0)
+    try:
+        tickets = [ctx.submit(scenes[r["scene"]]["h"], r["eyes"], r["width"], r["offset"], r["s"])
+                   for r in reqs]
+        assert len(set(tickets)) == len(tickets)
+        for t in tickets:
+            assert ctx.wait(t, 60000)
+        rng = np.random.default_rng(721)
+        for q, (t, r) in enumerate(zip(tickets, reqs)):
+            got = pair_keys_from_gpu(ctx.result(t))
+            sc = scenes[r["scene"]]
+            want = _plain_keys(ctx, sc["h"], _dev(ctx, r["eyes"]), r["s"], r["width"], r["offset"])
+            assert np.array_equal(got, want), "request %d" % q
+            _, n, info = ctx.poll(t)
+            assert n == got.size and info["n_pairs"] == n and info["launches"] >= 1
+            assert info["submit_s"] <= info["start_s"] <= info["done_s"]
+            if q % 12 == 0:
+                sel = np.sort(rng.choice(r["eyes"].shape[0], 8, replace=False)).astype(np.uint32)
+                o = _oracle_keys(orc, sc["lights"], r["eyes"], sel, r["width"], r["offset"], r["s"])
+                assert np.array_equal(select_pairs_of_eyes(ctx.result(t), sel), o)
+            ctx.release(t)
+        st = ctx.server_stats()
+        assert st["submitted"] == st["completed"] == len(reqs)
+        assert 1 <= st["launches"] <= len(reqs) + st["retries"]
+        assert st["p99_ms"] >= st["p50_ms"] > 0
+    finally:
+        ctx.server_stop()
+    for sc in scenes:
+        sc["h"].free()
+
+
+def test_served_overflow_is_retried_exactly(ctx):
+    scenes = _served_setup(ctx, sizes=(1 << 14,))
+    reqs = _requests(scenes, 6, 730, lo=9.0, hi=10.0)
+    ctx.server_start(hbm_budget_bytes=1 << 28, max_inflight=1, pairs_per_eye_guess=1e-6)
+    try:
+        ts = [ctx.submit(scenes[0]["h"], r["eyes"], 64, r["offset"], r["s"]) for r in reqs]
+        for t, r in zip(ts, reqs):
+            assert ctx.wait(t, 60000)
+            want = _plain_keys(ctx, scenes[0]["h"], _dev(ctx, r["eyes"]), r["s"], 64, r["offset"])
+            assert np.array_equal(pair_keys_from_gpu(ctx.result(t)), want)
+            if want.size > 4096 * 2:
+                assert ctx.poll(t)[2]["launches"] == 2 or ctx.server_stats()["retries"] >= 1
+            ctx.release(t)
+        assert ctx.server_stats()["retries"] >= 1
+    finally:
+        ctx.server_stop()
+    scenes[0]["h"].free()
+
+
+def test_served_admission_cancel_and_release(ctx, hrr):
+    """A held result blocks a request whose output reservation needs the whole
+    budget; that request stays queued (so it can be cancelled) until the
+    result is released.  The blocked requests use a second hierarchy that no
+    request has finished on, so their reservation is the configured guess."""
+    rng = np.random.default_rng(740)
+    lights = rng.random((1 << 12, 3)).astype(np.float32)
+    h = ctx.build_hierarchy(lights)
+    h2 = ctx.build_hierarchy(lights)
+    small = rng.random((64, 3)).astype(np.float32)
+    big = rng.random((1000, 3)).astype(np.float32)
+    budget = 8 << 20
+    ctx.server_start(hbm_budget_bytes=budget, max_inflight=1, pairs_per_eye_guess=1e4)
+    try:
+        ta = ctx.submit(h, small, 64, 0, 1e-3)
+        assert ctx.wait(ta, 60000)
+        assert ctx.poll(ta)[1] > 0
+        tb = ctx.submit(h2, big, 64, 0, 1e-3)
+        assert not ctx.wait(tb, 300)           # queued behind the held result
+        assert ctx.cancel(tb) == hrr.HRR_OK
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.poll(tb)
+        assert ei.value.status == hrr.HRR_E_CANCELLED
+        ctx.release(tb)
+        tc = ctx.submit(h2, big, 64, 0, 1e-3)
+        assert not ctx.wait(tc, 300)
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.release(tc)                    # still queued
+        assert ei.value.status == hrr.HRR_E_BUSY
+        ctx.release(ta)                        # frees the arena: tc runs
+        assert ctx.wait(tc, 60000)
+        want = _plain_keys(ctx, h2, _dev(ctx, big), 1e-3, 64)
+        assert np.array_equal(pair_keys_from_gpu(ctx.result(tc)), want)
+        assert ctx.cancel(tc) == hrr.HRR_E_BUSY    # already complete
+        ctx.release(tc)
+        # eyes that can never fit are rejected at submit
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.submit(h, rng.random((budget // 12 + 1, 3)).astype(np.float32), 64, 0, 1e-3)
+        assert ei.value.status == hrr.HRR_E_NOMEM
+        # a result larger than the whole budget fails the request, not the server
+        huge = rng.random((1 << 16, 3)).astype(np.float32)
+        td = ctx.submit(h, huge, 64, 0, 1.0)   # p = 1 for most pairs: ~2^28 pairs
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.wait(td, 60000)
+        assert ei.value.status == hrr.HRR_E_NOMEM
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.poll(td)
+        assert ei.value.status == hrr.HRR_E_NOMEM
+        ctx.release(td)
+        # the server still serves
+        te = ctx.submit(h, small, 64, 7, 1e-3)
+        assert ctx.wait(te, 60000)
+        want = _plain_keys(ctx, h, _dev(ctx, small), 1e-3, 64, offset=7)
+        assert np.array_equal(pair_keys_from_gpu(ctx.result(te)), want)
+        ctx.release(te)
+        st = ctx.server_stats()
+        assert st["cancelled"] == 1 and st["rejected"] == 1 and st["peak_bytes"] <= budget
+    finally:
+        ctx.server_stop()
+    h.free()
+    h2.free()
+
+
+def test_served_from_many_threads(ctx):
+    scenes = _served_setup(ctx, sizes=(1 << 13, 1 << 15))
+    reqs = _requests(scenes, 40, 750, lo=6.0, hi=10.0)
+    ctx.server_start(hbm_budget_bytes=1 << 30, max_inflight=3, max_batch_items=8)
+    results = {}
+    errors = []
+
+    def client(part):
+        try:
+            for q in part:
+                r = reqs[q]
+                t = ctx.submit(scenes[r["scene"]]["h"], r["eyes"], 64, r["offset"], r["s"])
+                assert ctx.wait(t, 60000)
+                results[q] = pair_keys_from_gpu(ctx.result(t))
+                ctx.release(t)
+        except Exception as ex:   # reported below
+            errors.append(ex)
+
+    try:
+        ths = [threading.Thread(target=client, args=(list(range(k, len(reqs), 4)),))
+               for k in range(4)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        assert not errors, errors
+        for q, r in enumerate(reqs):
+            want = _plain_keys(ctx, scenes[r["scene"]]["h"], _dev(ctx, r["eyes"]), r["s"], 64,
+                               r["offset"])
+            assert np.array_equal(results[q], want), "request %d" % q
+    finally:
+        ctx.server_stop()
+    for sc in scenes:
+        sc["h"].free()
+
+
+def test_server_lifecycle_errors(ctx, hrr):
+    h = ctx.build_hierarchy(np.random.default_rng(1).random((256, 3)).astype(np.float32))
+    eyes = np.random.default_rng(2).random((16, 3)).astype(np.float32)
+    with pytest.raises(hrr.HrrError) as ei:
+        ctx.submit(h, eyes, 64, 0, 1e-3)
+    assert ei.value.status == hrr.HRR_E_BUSY
+    with pytest.raises(hrr.HrrError) as ei:
+        ctx.server_start(hbm_budget_bytes=1 << 10)
+    assert ei.value.status == hrr.HRR_E_INVALID
+    ctx.server_start(hbm_budget_bytes=1 << 24)
+    try:
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.server_start(hbm_budget_bytes=1 << 24)
+        assert ei.value.status == hrr.HRR_E_BUSY
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.poll(987654321)
+        assert ei.value.status == hrr.HRR_E_INVALID
+        bad = eyes.copy()
+        bad[3, 1] = np.nan
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.submit(h, bad, 64, 0, 1e-3)
+        assert ei.value.status == hrr.HRR_E_INVALID
+        with pytest.raises(hrr.HrrError) as ei:
+            ctx.submit(h, eyes, 64, 0, 0.0)
+        assert ei.value.status == hrr.HRR_E_INVALID
+        t = ctx.submit(h, np.zeros((0, 3), np.float32), 64, 0, 1e-3)
+        assert ctx.wait(t, 60000) and ctx.poll(t)[1] == 0
+        ctx.release(t)
+    finally:
+        ctx.server_stop()
+    ctx.server_stop()          # stopping twice is fine
+    with pytest.raises(hrr.HrrError) as ei:
+        ctx.server_stats()
+    assert ei.value.status == hrr.HRR_E_BUSY
+    h.free()

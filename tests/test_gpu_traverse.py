@@ -171,6 +171,25 @@ def test_overflow_reports_true_count(ctx, tiny, tiny_oracle):
     h.free()
 
 
+@pytest.mark.parametrize("extra", [1, 77, 1000, 100003, -1])
+def test_capacity_above_the_count(ctx, tiny, tiny_oracle, extra):
+    """Capacity larger than the count: output chunks straddle the capacity
+    and the pairs past it live in the slack area until compaction; the first
+    count positions must hold exactly the accepted set (with weights)."""
+    import torch
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=1)
+    eyes = _eyes_t(ctx, tiny["eyes"])
+    total = tiny_oracle["keys"].size
+    cap = 2 * total if extra < 0 else total + extra
+    buf = torch.full((cap, 2), -7, dtype=torch.int32, device=ctx.torch_device)
+    w = torch.full((cap,), -7.0, dtype=torch.float32, device=ctx.torch_device)
+    pairs, n, _, wt = ctx.traverse(h, eyes, tiny["s"], tiny["width"], pairs=buf, weights=w)
+    assert n == total
+    assert np.array_equal(pair_keys_from_gpu(pairs), tiny_oracle["keys"])
+    assert bool((wt >= 1.0).all())
+    h.free()
+
+
 @pytest.mark.parametrize("n_l,leaf", [(1, 1), (2, 1), (3, 1), (5, 8), (8, 8), (9, 8), (17, 4)])
 def test_small_and_root_leaf_hierarchies(ctx, orc, n_l, leaf):
     lights = synth.uniform_points(n_l, 900 + n_l)
