@@ -67,6 +67,26 @@ __device__ __forceinline__ void wave_sync() {
 
 // squared distance from the eye to the box [lo, hi] (0 inside), summed
 // (x + y) + z; for a one-point box this is the pair's own d^2 bit for bit.
+// Hierarchy records and lights always live in device global memory; loading
+// them through an address-space-1 pointer makes the compiler emit global
+// loads instead of generic (flat) ones, which would also tie up the LDS
+// counter that the stack operations wait on.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+// DPP control: quad_perm(1, 0, 3, 2) -- every lane reads its pair partner.
+constexpr int kDppSwapPairs = 0xB1;
+
+__device__ __forceinline__ float swap_pairs(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), kDppSwapPairs, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float4 swap_pairs(float4 v) {
+    return make_float4(swap_pairs(v.x), swap_pairs(v.y), swap_pairs(v.z), swap_pairs(v.w));
+}
+
+__device__ __forceinline__ float4 load_global4(const float4* p, uint32_t i) {
+    const f32x4 v = ((const __attribute__((address_space(1))) f32x4*)(p))[i];
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
 __device__ __forceinline__ float box_d2(float ex, float ey, float ez, float lx, float ly, float lz,
                                         float hx, float hy, float hz) {
     const float dx = fmaxf(fmaxf(lx - ex, ex - hx), 0.0f);
@@ -96,37 +116,47 @@ __device__ __forceinline__ bool keeps(uint32_t v, float p) {
 
 constexpr float kBoxMargin = 1.0f + 0x1p-20f;
 
-// ---- fast bounds with v_rcp_f32 --------------------------------------------
+// ---- product-form keep test ------------------------------------------------
 //
-// The IEEE quotient s / d2 costs about ten VALU instructions.  v_rcp_f32
-// returns 1/d2 within 1 ulp (relative error <= 2^-23, CDNA ISA), so
-// q' = s * rcp(d2) is within 2^-23 + 2^-24 of s / d2 and within ~2^-22 of the
-// rounded quotient.  Comparing the fixed-point random number against q' 2^32
-// with a relative band of 2^-19 on either side therefore decides the exact
-// test whenever the value lies outside the band; inside it (about 2^-18 of the
-// cases) the exact IEEE path decides.  Extreme magnitudes (d2 > 2^100 or
-// q' < 2^-60, never met in the unit cube) always take the exact path so that
-// no underflow of rcp can flip a decision.
-constexpr float kTwo32Lo = 0x1p32f * (1.0f - 0x1p-19f);
-constexpr float kTwo32Hi = 0x1p32f * (1.0f + 0x1p-19f);
+// With x = fl(s / d2) 2^32 the pair is kept iff v < x (v is an integer, so
+// v < ceil(x) is the same as v < x).  Instead of the IEEE quotient (about ten
+// VALU instructions) the kernel compares the product P = fl(fl(v) d2) with
+// two per-item constants, t_cull >= S (1 + 2^-18) and t_keep <= S (1 - 2^-18),
+// S = s 2^32.  Each of fl(v), the product and fl(s / d2) has a relative error
+// of at most 2^-24, so
+//   P > t_cull  implies  v > (s / d2) 2^32 (1 + 2^-24) >= x   (culled), and
+//   P < t_keep  implies  v < (s / d2) 2^32 (1 - 2^-24) <= x   (kept).
+// For d2 <= s (p = 1) the first never holds, since fl(v) d2 <= 2^32 s.
+// A box at squared distance d2 bounds every light inside it (each light's
+// squared distance, computed with the same monotone binary32 steps, is at
+// least d2), so "P > t_cull" culls a whole subtree safely; anything else
+// keeps the box.  A one-light test whose product falls between the two
+// constants (a relative band of about 2^-17 around the threshold) decides
+// with the IEEE quotient.  The product form is used only for
+// d2 <= d2_fast = s 2^60 (s / d2 stays a normal number, P cannot overflow);
+// beyond it, and for s outside [2^-60, 2^60], the IEEE path decides.
+
+// Product-form part of the keep test, with selects only: sets `keep` and
+// returns false when decided, returns true when the IEEE path must decide.
+__device__ __forceinline__ bool rr_fast(uint32_t v, const ItemDesc& D, float d2, bool exact, bool& keep) {
+    const float P = (float)v * d2;
+    const bool fast = d2 <= D.d2_fast;
+    const bool cull = fast && P > D.t_cull;
+    const bool sure = fast && (!exact || P < D.t_keep);
+    keep = !cull;
+    return !cull && !sure;
+}
 
 // Keep test of value v at squared distance d2.
 //   exact = true : one light; the result equals keeps(v, min(1, s / d2)).
-//   exact = false: a box; false only if no light in the box can keep v.  It
-//                  culls only when (float)v exceeds q' 2^32 (1 + 2^-19), which
-//                  implies v > p 2^32 for every light at distance^2 >= d2.
-// d2 <= s means s / d2 >= 1 (p = 1): always kept.
-__device__ __forceinline__ bool rr_test(uint32_t v, float s, float d2, bool exact) {
-    if (d2 <= s) return true;
-    if (d2 <= 0x1p100f) {
-        const float q = s * __builtin_amdgcn_rcpf(d2);
-        if (q >= 0x1p-60f) {
-            const float V = (float)v;
-            if (V > q * kTwo32Hi) return false;
-            if (!exact || V < q * kTwo32Lo) return true;
-        }
+//   exact = false: a box; false only if no light in the box can keep v.
+__device__ __forceinline__ bool rr_test(uint32_t v, const ItemDesc& D, float d2, bool exact) {
+    if (d2 <= D.d2_fast) {
+        const float P = (float)v * d2;
+        if (P > D.t_cull) return false;
+        if (!exact || P < D.t_keep) return true;
     }
-    return keeps(v, accept_p(s, d2, exact ? 1.0f : kBoxMargin));
+    return keeps(v, accept_p(D.s, d2, exact ? 1.0f : kBoxMargin));
 }
 
 // Fixed-point golden-ratio lattice alpha = round(2^32 (sqrt(5) - 1) / 2).
@@ -435,9 +465,9 @@ __device__ __forceinline__ void leaf_lights(OutState& O, const ItemDesc& D, cons
         float w = 0.0f;
         if (act) {
             i = q < ln ? la + q : ra + (q - ln);
-            const float4 P = reinterpret_cast<const float4*>(D.lights)[i];
+            const float4 P = load_global4(reinterpret_cast<const float4*>(D.lights), i);
             const float d2 = box_d2(E.ex, E.ey, E.ez, P.x, P.y, P.z, P.x, P.y, P.z);
-            emit = rr_test(rotated(i, E.R), D.s, d2, true);
+            emit = rr_test(rotated(i, E.R), D, d2, true);
             if (W) w = 1.0f / accept_p(D.s, d2, 1.0f);
             ++tests;
         }
@@ -550,9 +580,9 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
                     bool emit = false;
                     float w = 0.0f;
                     if (a1) {
-                        const float4 P = reinterpret_cast<const float4*>(D.lights)[lane];
+                        const float4 P = load_global4(reinterpret_cast<const float4*>(D.lights), lane);
                         const float d2 = box_d2(E.ex, E.ey, E.ez, P.x, P.y, P.z, P.x, P.y, P.z);
-                        emit = rr_test(rotated(lane, E.R), s, d2, true);
+                        emit = rr_test(rotated(lane, E.R), D, d2, true);
                         if (W) w = 1.0f / accept_p(s, d2, 1.0f);
                         ++tests;
                     }
@@ -569,7 +599,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
                 k0 = rmq<METHOD>(0u, N, E.kr);
                 const float d2 = box_d2(E.ex, E.ey, E.ez, D.root_lo[0], D.root_lo[1], D.root_lo[2],
                                         D.root_hi[0], D.root_hi[1], D.root_hi[2]);
-                push = rr_test(rotated(k0, E.R), s, d2, false);
+                push = rr_test(rotated(k0, E.R), D, d2, false);
                 if (STATS) ++st_rmq;
             }
             const uint64_t m = ballot(push);
@@ -606,9 +636,32 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
             uint32_t kL = 0, kR = 0, a = 0, c = 0, b = 0, rightIdx = 0;
             uint32_t mlA = 0, mlN = 0, mrA = 0, mrN = 0;   // multi-light leaf ranges to test
             float wL = 0.0f, wR = 0.0f;
+            // Node records.  Every 16-byte load of a lane that hits its own
+            // cache line costs one vector-L1 tag lookup, and those lookups
+            // bound this loop; so the two lanes of a pair fetch each of their
+            // two records as 32-byte halves (one lookup per pair and load)
+            // and then swap halves with a DPP lane exchange.
+            float4 q0, q1, q2, q3;
+            {
+                const bool odd = (lane & 1u) != 0u;
+                const uint32_t partner = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, kDppSwapPairs, 0xF, 0xF, false);
+                const uint32_t n_even = odd ? partner : node;   // record of the pair's even lane
+                const uint32_t n_odd = odd ? node : partner;    // record of the pair's odd lane
+                const float4* re = reinterpret_cast<const float4*>(D.nodes + n_even);
+                const float4* ro = reinterpret_cast<const float4*>(D.nodes + n_odd);
+                const uint32_t h = odd ? 1u : 0u;
+                float4 e02 = make_float4(0.f, 0.f, 0.f, 0.f), e13 = e02, o02 = e02, o13 = e02;
+                if ((lane & ~1u) < n) { e02 = load_global4(re, h); e13 = load_global4(re, 2u + h); }
+                if ((lane | 1u) < n) { o02 = load_global4(ro, h); o13 = load_global4(ro, 2u + h); }
+                // even lane holds chunks 0, 2 of both records, odd lane chunks 1, 3
+                const float4 r1 = swap_pairs(odd ? e02 : o02);
+                const float4 r2 = swap_pairs(odd ? e13 : o13);
+                q0 = odd ? r1 : e02;
+                q1 = odd ? o02 : r1;
+                q2 = odd ? r2 : e13;
+                q3 = odd ? o13 : r2;
+            }
             if (act) {
-                const float4* rec = reinterpret_cast<const float4*>(D.nodes + node);
-                const float4 q0 = rec[0], q1 = rec[1], q2 = rec[2], q3 = rec[3];
                 a = __float_as_uint(q0.w);
                 c = __float_as_uint(q1.w);
                 b = __float_as_uint(q2.w);
@@ -629,8 +682,14 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravAr
                 const bool leafL = nL <= leaf, leafR = nR <= leaf;
                 const float d2L = box_d2(E.ex, E.ey, E.ez, q0.x, q0.y, q0.z, q1.x, q1.y, q1.z);
                 const float d2R = box_d2(E.ex, E.ey, E.ez, q2.x, q2.y, q2.z, q3.x, q3.y, q3.z);
-                const bool sL = rr_test(rotated(kL, E.R), s, d2L, nL == 1u);
-                const bool sR = rr_test(rotated(kR, E.R), s, d2R, nR == 1u);
+                const uint32_t vL = rotated(kL, E.R), vR = rotated(kR, E.R);
+                bool sL, sR;
+                const bool openL = rr_fast(vL, D, d2L, nL == 1u, sL);
+                const bool openR = rr_fast(vR, D, d2R, nR == 1u, sR);
+                if (openL || openR) {   // rare: one shared block for the IEEE decisions
+                    if (openL) sL = keeps(vL, accept_p(s, d2L, nL == 1u ? 1.0f : kBoxMargin));
+                    if (openR) sR = keeps(vR, accept_p(s, d2R, nR == 1u ? 1.0f : kBoxMargin));
+                }
                 pushL = sL && !leafL;
                 pushR = sR && !leafR;
                 emitL = sL && nL == 1u;

@@ -31,6 +31,22 @@ bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
 constexpr unsigned long long kSlackFlag = 1ull << 63;
 
+// Bounds of the kernel's product-form keep test for one s (the derivation is
+// beside rr_test in the kernels): t_cull >= s 2^32 (1 + 2^-18) and
+// t_keep <= s 2^32 (1 - 2^-18), both rounded outward to binary32; the test is
+// used for d2 <= d2_fast = s 2^60 (at most 2^80) only, and never for an s
+// outside [2^-60, 2^60] (then d2_fast = 0 sends every test to the IEEE path).
+void product_test_bounds(float s, float* t_cull, float* t_keep, float* d2_fast) {
+    const double S = (double)s * 4294967296.0;
+    float hi = (float)(S * (1.0 + 0x1p-18));
+    if ((double)hi < S * (1.0 + 0x1p-18)) hi = nextafterf(hi, INFINITY);
+    float lo = (float)(S * (1.0 - 0x1p-18));
+    if ((double)lo > S * (1.0 - 0x1p-18)) lo = nextafterf(lo, 0.0f);
+    *t_cull = hi;
+    *t_keep = lo;
+    *d2_fast = (s >= 0x1p-60f && s <= 0x1p60f) ? std::min((float)((double)s * 0x1p60), 0x1p80f) : 0.0f;
+}
+
 }  // namespace
 
 hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
@@ -194,6 +210,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         D.n_samples = n_samples;
         D.psi_s0 = psi_s0;
         D.s = it.s;
+        product_test_bounds(it.s, &D.t_cull, &D.t_keep, &D.d2_fast);
         for (int q = 0; q < 3; ++q) {
             D.root_lo[q] = h->box[q];
             D.root_hi[q] = h->box[3 + q];

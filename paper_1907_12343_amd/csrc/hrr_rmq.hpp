@@ -189,12 +189,13 @@ HRR_HD uint32_t rmq_paper_pruned(uint32_t a, uint32_t b, uint32_t kr) {
 
 // Index with the most trailing zeros in [lo, hi] (lo <= hi): below the highest
 // bit where lo and hi differ, hi with that bit kept and the rest cleared --
-// unless lo itself is already zero from that bit down.
+// unless lo itself is already zero from that bit down.  Written with selects
+// only (no divergent branches on the GPU).
 HRR_HD uint32_t most_trailing_zeros(uint32_t lo, uint32_t hi) {
-    if (lo == hi) return lo;
-    const int h = top_bit(lo ^ hi);
-    if ((lo & low_mask(h + 1)) == 0u) return lo;
-    return hi & ~low_mask(h);
+    const uint32_t x = lo ^ hi;
+    const int h = x ? top_bit(x) : 0;
+    const uint32_t r = hi & ~low_mask(h);
+    return (x == 0u || (lo & low_mask(h + 1)) == 0u) ? lo : r;
 }
 
 // Same result in O(1): the candidate set for "first difference at bit i" is
@@ -245,28 +246,33 @@ HRR_HD uint32_t rmq_direct(uint32_t a, uint32_t b, uint32_t kr) {
 // reflected-smallest member.  No class: the range's reflected-smallest index,
 // the one with the most trailing zeros (Algorithm 1's answer).
 HRR_HD uint32_t rmq_paper_select(uint32_t a, uint32_t b, uint32_t kr) {
-    if (in_range(kr, a, b)) return kr;
+    // Every case is evaluated with selects; only the refinement walk, needed
+    // when no single-member class wins, is a (short) loop.
     const uint32_t len = b - a;
-    const int g = top_bit(len);
     const uint32_t d = kr - a;
-    const uint32_t dlow = d & low_mask(g + 1);
-    if (g < 31) {
-        const uint32_t dhi = d >> (g + 1);
-        if (dhi) {
-            const int i = bottom_bit(dhi) + g + 1;
-            if (!((kr >> i) & 1u) && dlow < len) return a + ((d & low_mask(i + 1)) ^ (1u << i));
-        }
-    }
-    if (!((kr >> g) & 1u)) {
-        const uint32_t t = dlow ^ (1u << g);
-        if (t < len) return a + t;
-    }
+    const bool first = d < len;                  // k_r itself is in the range
+    const int g = top_bit(len);
+    const uint32_t mg = low_mask(g + 1);
+    const uint32_t dlow = d & mg;
+    const uint32_t dhi = d & ~mg;
+    // above g: the lowest set bit i of (k_r - a) above g; its class holds the
+    // single index a + ((d & low_mask(i + 1)) ^ 2^i) = a + dlow (the bits of d
+    // between g and i are zero and bit i is set)
+    const int i_hi = dhi ? bottom_bit(dhi) : 0;
+    const bool above = dhi != 0u && !((kr >> i_hi) & 1u) && dlow < len;
+    // at g: the single candidate a + (dlow ^ 2^g)
+    const uint32_t t_g = dlow ^ (1u << g);
+    const bool at_g = !((kr >> g) & 1u) && t_g < len;
+    // below g: every zero bit of k_r has a non-empty class; the highest wins
     const uint32_t z = ~kr & low_mask(g);
-    if (z) {
+    uint32_t k = most_trailing_zeros(a, b - 1u);   // no class: Algorithm 1's answer
+    if (!first && !above && !at_g && z != 0u) {
         const int i = top_bit(z);
-        return refine(seed_candidate(a, i, kr & low_mask(i)), i + 1, a, b);
+        k = refine(seed_candidate(a, i, kr & low_mask(i)), i + 1, a, b);
     }
-    return most_trailing_zeros(a, b - 1u);
+    k = at_g ? a + t_g : k;
+    k = above ? a + dlow : k;
+    return first ? kr : k;
 }
 
 // METHOD 0: the paper's sweeps, candidate positions selected bit-parallel,

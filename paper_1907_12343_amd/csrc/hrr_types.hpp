@@ -47,6 +47,9 @@ struct ItemDesc {
     uint32_t width, shift_offset, pixel_base, n_samples;
     uint32_t psi_s0, task_begin;
     float s;
+    // product-form keep test (set by the host): v is culled when
+    // float(v) * d2 > t_cull, kept (one light) when < t_keep, for d2 <= d2_fast
+    float t_cull, t_keep, d2_fast;
     float root_lo[3], root_hi[3];
 };
 
