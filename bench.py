@@ -76,21 +76,24 @@ def frame_workload(args):
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    kernel_ms = []
     _sync_all()
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        _, got, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, **kw)
+        # timing=True: the library brackets the traversal kernel with HIP
+        # events on this same stream
+        _, got, stt = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, timing=True, **kw)
         assert got == n
+        kernel_ms.append(stt["kernel_ms"])
     e1.record(stream)
     _sync_all()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    gpu_ms = e0.elapsed_time(e1) / args.steps
+    step_gpu_ms = e0.elapsed_time(e1) / args.steps
+    gpu_ms = sum(kernel_ms) / len(kernel_ms)
 
-    multi_leaf_tests = max(st["leaf_tests"] - 2 * st["node_visits"], 0)
-    ops = (st["node_visits"] * OPS_VISIT + st["rmq_calls"] * OPS_RMQ + multi_leaf_tests * OPS_LEAF
-           + n * OPS_PAIR)
+    ops = _ops_of(st, n)
     achieved = ops / (gpu_ms * 1e-3) / 1e12
     line = {
         "metric": "eye-vertex traversals/s",
@@ -112,20 +115,51 @@ def frame_workload(args):
         "pairs_per_s": n / (ms * 1e-3),
         "accepted_pairs": n,
         "kernel_ms": gpu_ms,
+        "step_gpu_ms": step_gpu_ms,
         "hierarchy_build_s": build_s,
         "units": {"node_visits": st["node_visits"], "rmq_calls": st["rmq_calls"],
                   "leaf_tests": st["leaf_tests"], "pairs": n},
         "algorithmic_lane_ops": ops,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": (None if args.traffic_kib is None
-                                 else (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0)},
+                     "traffic": _traffic_bytes(args)},
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_frame(fr, n_eyes, args)
     h.free()
     ctx.close()
     return line
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traverse_frame_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1907_12343_amd", "csrc", f)
+                  for f in ("hrr_kernels.hip", "hrr_rmq.hpp", "hrr_types.hpp")]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic_bytes(args):
+    """HBM bytes of one timed traversal launch: FETCH_SIZE + WRITE_SIZE from
+    rocprofv3 --pmc runs, scaled by the copy-kernel calibration, as recorded in
+    profiles/ together with the digest of the kernel sources they were taken
+    on; None when the kernel has changed since (or --traffic-kib overrides)."""
+    if args.traffic_kib is not None:
+        return (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sources_sha256") != kernel_source_digest():
+        return None
+    return (rec["fetch_kib_scaled"] + rec["write_kib_scaled"]) * 1024.0
 
 
 def cpu_baseline_frame(fr, n_eyes, args):
@@ -255,7 +289,14 @@ def batched_workload(args):
         _sync_all()
         return (time.perf_counter() - t0) * 1e3 / args.steps, e0.elapsed_time(e1) / args.steps
 
-    ms, gpu_ms = timed(lambda: ctx.traverse_batched(items, pairs))
+    kms = []
+
+    def batched():
+        _, stt = ctx.traverse_batched(items, pairs, timing=True)
+        kms.append(stt["kernel_ms"])
+
+    ms, step_gpu_ms = timed(batched)
+    gpu_ms = sum(kms[args.warmup:]) / max(len(kms) - args.warmup, 1)
 
     def plain():
         for k, (h, e, d) in enumerate(zip(hs, eyes, caches)):
@@ -275,7 +316,7 @@ def batched_workload(args):
                    "n_eyes": n_eyes, "n_lights": int(sizes.sum()), "leaf": leaf,
                    "tuned": tuned, "parallelism": "1 GPU"},
         "pairs_per_s": total / (ms * 1e-3), "accepted_pairs": total, "kernel_ms": gpu_ms,
-        "setup_s": setup_s,
+        "step_gpu_ms": step_gpu_ms, "setup_s": setup_s,
         "plain_launches": {"ms_per_step": ms_plain, "eyes_per_s": n_eyes / (ms_plain * 1e-3),
                            "speedup_of_batched": ms_plain / ms},
         "units": {k: st[k] for k in ("node_visits", "rmq_calls", "leaf_tests")},

@@ -166,6 +166,8 @@ typedef struct hrr_eyes {
 #define HRR_F_STATS 1u      /* count node visits, range minima, leaf tests (slower) */
 #define HRR_F_NO_REORDER 2u /* process eyes in index order instead of grouping them by space
                                (ablation; the result is the same either way) */
+#define HRR_F_TIMING 4u     /* time the traversal kernel alone with HIP events on the
+                               call's stream (hrr_stats.kernel_ms) */
 
 typedef struct hrr_traverse_opts {
     uint32_t eyes_per_wave; /* 0 = autotuned; else 1, 2, 4 or 8 eyes share one wavefront */
@@ -184,6 +186,7 @@ typedef struct hrr_stats {
     uint64_t leaf_tests;    /* exact per-light acceptance tests */
     uint64_t spills;        /* stack chunks moved between LDS and device memory */
     uint64_t max_stack;     /* deepest stack seen by any wave */
+    double kernel_ms;       /* traversal kernel duration with HRR_F_TIMING, else 0 */
 } hrr_stats;
 
 /* Hierarchical Russian roulette of every eye of `eyes` against `h`.

@@ -24,6 +24,7 @@ HRR_E_DEVICE, HRR_E_NOTREADY, HRR_E_CANCELLED, HRR_E_BUSY = 4, 5, 6, 7
 RMQ_PAPER, RMQ_DIRECT, RMQ_PAPER_FULL, RMQ_PAPER_LOOP = 0, 1, 2, 3
 F_STATS = 1
 F_NO_REORDER = 2
+F_TIMING = 4
 
 _u32, _u64, _i32, _f32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_float
 _P = ctypes.c_void_p
@@ -41,10 +42,12 @@ class HrrTraverseOpts(ctypes.Structure):
 
 class HrrStats(ctypes.Structure):
     _fields_ = [("eyes", _u64), ("pairs", _u64), ("node_visits", _u64), ("rmq_calls", _u64),
-                ("leaf_tests", _u64), ("spills", _u64), ("max_stack", _u64)]
+                ("leaf_tests", _u64), ("spills", _u64), ("max_stack", _u64),
+                ("kernel_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+        return {k: (float(getattr(self, k)) if t is ctypes.c_double else int(getattr(self, k)))
+                for k, t in self._fields_}
 
 
 class HrrHierarchyInfo(ctypes.Structure):
@@ -220,8 +223,8 @@ class Hierarchy:
 
 
 def _opts(eyes_per_wave=0, stack_entries=0, rmq_method=RMQ_PAPER, n_samples=1, psi_s0=0,
-          stats=False, reorder=True):
-    flags = (F_STATS if stats else 0) | (0 if reorder else F_NO_REORDER)
+          stats=False, reorder=True, timing=False):
+    flags = (F_STATS if stats else 0) | (0 if reorder else F_NO_REORDER) | (F_TIMING if timing else 0)
     return HrrTraverseOpts(eyes_per_wave, stack_entries, rmq_method, n_samples,
                            psi_s0 & 0xFFFFFFFF, flags)
 

@@ -94,6 +94,9 @@ void release_scratch(LaunchScratch& S) {
     if (S.h_pinned) (void)hipHostFree(S.h_pinned);
     S.h_pinned = nullptr;
     S.h_pinned_n = 0;
+    if (S.ev_begin) (void)hipEventDestroy(S.ev_begin);
+    if (S.ev_end) (void)hipEventDestroy(S.ev_end);
+    S.ev_begin = S.ev_end = nullptr;
 }
 
 void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes, uint32_t* epw,
@@ -330,7 +333,9 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
     const bool want_stats = opts && (opts->flags & HRR_F_STATS);
     LaunchScratch& S = ctx->scratch;
     const bool reorder = !(opts && (opts->flags & HRR_F_NO_REORDER));
-    hrr_status st = launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, reorder, pairs, weights, stream);
+    const bool timing = opts && (opts->flags & HRR_F_TIMING);
+    hrr_status st =
+        launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, reorder, pairs, weights, stream, timing);
     if (st != HRR_OK) return st;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "traverse");
     if ((st = finish_items(ctx, S, pairs, weights, stream)) != HRR_OK) return st;
@@ -346,6 +351,7 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
         memset(stats, 0, sizeof *stats);
         if (want_stats) fill_stats(S.stat, stats);
         stats->pairs = total;
+        stats->kernel_ms = timing ? timed_kernel_ms(S) : 0.0;
     }
     if (S.error & ERR_SPILL_OVERFLOW)
         return fail(HRR_E_DEVICE, "traversal kernel exhausted its stack spill region");

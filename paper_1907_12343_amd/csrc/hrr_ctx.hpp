@@ -82,6 +82,9 @@ struct LaunchScratch {
     std::vector<unsigned long long> stored;    // valid pairs stored at the front of each slice
     uint32_t error = 0;
     unsigned long long stat[ST_N] = {0};
+    // optional events around the traversal kernel (created on first use)
+    hipEvent_t ev_begin = nullptr, ev_end = nullptr;
+    bool timed = false;
 };
 
 struct Server;
@@ -120,7 +123,9 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
 // S.counts / S.stored / S.error / S.stat.
 hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
                         uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
-                        bool reorder, uint32_t* pairs, float* weights, hipStream_t stream);
+                        bool reorder, uint32_t* pairs, float* weights, hipStream_t stream, bool timing = false);
+// Duration of the last timed traversal kernel of S (after the stream has synchronised), ms.
+double timed_kernel_ms(LaunchScratch& S);
 hrr_status finish_items(hrr_ctx* ctx, LaunchScratch& S, uint32_t* pairs, float* weights, hipStream_t stream);
 
 void release_scratch(LaunchScratch& S);

@@ -475,8 +475,12 @@ __device__ __forceinline__ void leaf_lights(OutState& O, const ItemDesc& D, cons
     }
 }
 
+// The walk is bound by memory latency and the vector-memory pipeline, so
+// resident waves matter more than a few spilled registers: ask for 7 waves
+// per SIMD (at most 72 VGPRs) for the one-eye-per-wave form.
 template <int EPW, int METHOD, bool STATS, bool W>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) void traverse_kernel(TravArgs A) {
+__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(EPW == 1 ? 7 : 1, 8)))
+void traverse_kernel(TravArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     // dynamic LDS: task table (n_items + 1 entries, padded to 16 bytes), then one area per wave
     uint32_t* task_begin_lds = reinterpret_cast<uint32_t*>(smem);

@@ -51,8 +51,9 @@ void product_test_bounds(float s, float* t_cull, float* t_keep, float* d2_fast) 
 
 hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
                         uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
-                        bool reorder, uint32_t* pairs, float* weights, hipStream_t stream) {
+                        bool reorder, uint32_t* pairs, float* weights, hipStream_t stream, bool timing) {
     const size_t n = items.size();
+    S.timed = false;
     if (n == 0 || n > kMaxItemsPerLaunch)
         return fail(HRR_E_INVALID, "items per launch must be in [1, %u]", kMaxItemsPerLaunch);
     if (!(epw == 1 || epw == 2 || epw == 4 || epw == 8))
@@ -292,8 +293,17 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         A.lds_per_wave = (uint32_t)lds_wave;
         A.stats = stats ? d_misc + 2 : nullptr;
         A.error = reinterpret_cast<uint32_t*>(d_misc + 1);
+        if (timing) {
+            if (!S.ev_begin && (e = hipEventCreate(&S.ev_begin)) != hipSuccess) return hip_fail(e, "timing event");
+            if (!S.ev_end && (e = hipEventCreate(&S.ev_end)) != hipSuccess) return hip_fail(e, "timing event");
+            if ((e = hipEventRecord(S.ev_begin, stream)) != hipSuccess) return hip_fail(e, "timing event");
+        }
         if ((e = hrr_launch_traverse(&A, epw, method, stats, with_w, blocks, stream)) != hipSuccess)
             return hip_fail(e, "traverse launch");
+        if (timing) {
+            if ((e = hipEventRecord(S.ev_end, stream)) != hipSuccess) return hip_fail(e, "timing event");
+            S.timed = true;
+        }
     }
     if ((e = hipMemcpyAsync(S.h_pinned, d_counters, n * CNT_STRIDE * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             stream)) != hipSuccess)
@@ -302,6 +312,13 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
                             hipMemcpyDeviceToHost, stream)) != hipSuccess)
         return hip_fail(e, "read status");
     return HRR_OK;
+}
+
+double timed_kernel_ms(LaunchScratch& S) {
+    if (!S.timed) return 0.0;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, S.ev_begin, S.ev_end) != hipSuccess) return 0.0;
+    return (double)ms;
 }
 
 hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weights, hipStream_t stream) {
