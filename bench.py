@@ -242,7 +242,8 @@ def batched_workload(args):
     """256 independent caches (own mixture, 2^U[10,20] lights, 2^U[10,16]
     eyes, s = 1e-4) in ONE persistent launch, against 256 plain launches of
     the same items on the same GPU.  The launch shape and the leaf size come
-    from the autotuner, run once on a mid-size cache before timing."""
+    from the autotuner, run once before timing on the cache with the most
+    estimated work (eyes x lights^0.6)."""
     import numpy as np
     import torch
     import paper_1907_12343_amd as hrr
@@ -251,11 +252,12 @@ def batched_workload(args):
     ctx = hrr.Context(synth.dither_tile(100), device=0)
     caches = [synth.batched_cache(c) for c in range(256)]
     sizes = np.array([d["lights"].shape[0] for d in caches])
-    probe = caches[int(np.argsort(sizes)[len(sizes) // 2])]
+    work = np.array([d["eyes"].shape[0] * d["lights"].shape[0] ** 0.6 for d in caches])
+    probe = caches[int(np.argmax(work))]   # tune on the cache that dominates the launch
     t0 = time.time()
     cand = [ctx.build_hierarchy(probe["lights"], leaf_size=L) for L in (1, 2, 4, 8)]
     pe = torch.from_numpy(probe["eyes"]).to("cuda:0")
-    tuned = ctx.autotune(cand, pe, probe["s"], probe["width"], max_probe_eyes=8192)
+    tuned = ctx.autotune(cand, pe, probe["s"], probe["width"], max_probe_eyes=32768)
     for h in cand:
         h.free()
     leaf = tuned["leaf_size"]

@@ -94,6 +94,9 @@ void release_scratch(LaunchScratch& S) {
     if (S.h_pinned) (void)hipHostFree(S.h_pinned);
     S.h_pinned = nullptr;
     S.h_pinned_n = 0;
+    if (S.h_partials) (void)hipHostFree(S.h_partials);
+    S.h_partials = nullptr;
+    S.h_partials_n = 0;
     if (S.ev_begin) (void)hipEventDestroy(S.ev_begin);
     if (S.ev_end) (void)hipEventDestroy(S.ev_end);
     S.ev_begin = S.ev_end = nullptr;

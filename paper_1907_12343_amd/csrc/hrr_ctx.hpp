@@ -71,8 +71,10 @@ struct LaunchScratch {
     std::vector<unsigned long long> h_partial_off;   // per item, first entry in `partials`
     unsigned long long* h_pinned = nullptr;          // pinned staging / readback area
     size_t h_pinned_n = 0;
-    std::vector<unsigned long long> h_partials;       // host copy for hole filling
+    unsigned long long* h_partials = nullptr;         // pinned host copy for hole filling
+    size_t h_partials_n = 0;
     std::vector<unsigned long long> h_segments;
+    std::vector<unsigned long long> h_fill;           // fill of the chunks past an item's length
     std::vector<ItemMeta> meta;
     size_t n_items = 0;
     bool with_weights = false;

@@ -515,8 +515,8 @@ void traverse_kernel(TravArgs A) {
     uint32_t q = blockIdx.x % kQueues;
     uint32_t queues_left = kQueues;
     for (;;) {
-        const uint32_t q_lo = (uint32_t)((uint64_t)A.n_tasks * q / kQueues);
-        const uint32_t q_hi = (uint32_t)((uint64_t)A.n_tasks * (q + 1) / kQueues);
+        const uint32_t q_lo = A.queue_begin[q];
+        const uint32_t q_hi = A.queue_begin[q + 1];
         uint32_t t = 0;
         if (lane == 0) t = atomicAdd(A.queues + q * kQueueStride, 1u);
         t = q_lo + uni(t);

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <vector>
 
+#include "hrr_compact.hpp"
 #include "hrr_ctx.hpp"
 
 extern "C" hipError_t hrr_launch_traverse(const hrr::TravArgs* A, uint32_t eyes_per_wave, uint32_t method,
@@ -28,8 +29,6 @@ namespace hrr {
 namespace {
 
 bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
-
-constexpr unsigned long long kSlackFlag = 1ull << 63;
 
 // Bounds of the kernel's product-form keep test for one s (the derivation is
 // beside rr_test in the kernels): t_cull >= s 2^32 (1 + 2^-18) and
@@ -179,14 +178,55 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     unsigned long long* d_misc = static_cast<unsigned long long*>(S.misc.p);
     unsigned long long* d_partials = static_cast<unsigned long long*>(S.partials.p);
 
+    // ---- task order and work queues ----
+    // Items are laid out in the task list by decreasing cost per task (light
+    // count), and the eight queues get slices of roughly equal estimated cost
+    // (cost of a task ~ n_lights^0.6, the growth of node visits per eye):
+    // every queue starts with its heaviest eyes and ends with light ones, so
+    // the launch's tail is made of short tasks.  One item keeps equal slices.
+    std::vector<uint32_t> torder(n);
+    for (size_t k = 0; k < n; ++k) torder[k] = (uint32_t)k;
+    std::stable_sort(torder.begin(), torder.end(), [&](uint32_t x, uint32_t y) {
+        return items[x].h->n_lights > items[y].h->n_lights;
+    });
+    std::vector<double> task_cost(n);
+    double total_cost = 0.0;
+    for (size_t k = 0; k < n; ++k) {
+        task_cost[k] = pow((double)std::max<uint32_t>(items[k].h->n_lights, 1u), 0.6);
+        total_cost += task_cost[k] * (double)tasks_of[k];
+    }
+    std::vector<uint32_t> begin_of(n);
+    uint32_t qbegin[kQueues + 1];
+    {
+        uint64_t tb = 0;
+        double cum = 0.0;
+        uint32_t g = 1;
+        qbegin[0] = 0;
+        for (size_t pos = 0; pos < n; ++pos) {
+            const uint32_t k = torder[pos];
+            begin_of[k] = (uint32_t)tb;
+            const double c = task_cost[k], item_cost = c * (double)tasks_of[k];
+            while (g < kQueues && cum + item_cost >= total_cost * g / kQueues) {
+                const double need = total_cost * g / kQueues - cum;
+                const uint64_t at = tb + std::min<uint64_t>(tasks_of[k], (uint64_t)ceil(need / c));
+                qbegin[g] = (uint32_t)std::max<uint64_t>(at, qbegin[g - 1]);
+                ++g;
+            }
+            tb += tasks_of[k];
+            cum += item_cost;
+        }
+        for (; g <= kQueues; ++g) qbegin[g] = (uint32_t)tasks;
+        qbegin[kQueues] = (uint32_t)tasks;
+    }
+
     S.h_items.assign(n, ItemDesc{});
     S.h_task_begin.assign(n + 1, 0);
-    uint64_t tb = 0;
-    for (size_t k = 0; k < n; ++k) {
+    for (size_t pos = 0; pos < n; ++pos) {
+        const size_t k = torder[pos];
         const HostItem& it = items[k];
         const hrr_hierarchy* h = it.h;
         const ItemMeta& m = M[k];
-        ItemDesc& D = S.h_items[k];
+        ItemDesc& D = S.h_items[pos];
         D.nodes = h->d_nodes;
         D.lights = h->d_lights;
         D.eyes = it.eyes.xyz;
@@ -216,9 +256,8 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
             D.root_lo[q] = h->box[q];
             D.root_hi[q] = h->box[3 + q];
         }
-        D.task_begin = (uint32_t)tb;
-        S.h_task_begin[k] = (uint32_t)tb;
-        tb += tasks_of[k];
+        D.task_begin = begin_of[k];
+        S.h_task_begin[pos] = begin_of[k];
     }
     S.h_task_begin[n] = (uint32_t)tasks;
 
@@ -285,6 +324,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         A.task_begin = static_cast<const uint32_t*>(S.task_begin.p);
         A.n_items = (uint32_t)n;
         A.n_tasks = (uint32_t)tasks;
+        for (uint32_t q = 0; q <= kQueues; ++q) A.queue_begin[q] = qbegin[q];
         A.queues = static_cast<uint32_t*>(S.queues.p);
         A.tile = ctx->d_tile;
         A.spill = static_cast<unsigned long long*>(S.spill.p);
@@ -333,6 +373,34 @@ hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weig
 
     hipError_t e;
     S.h_segments.clear();
+    // read every item's list of partly filled chunks with one synchronisation
+    std::vector<size_t> part_at(n + 1, 0);
+    for (size_t k = 0; k < n; ++k) {
+        const unsigned long long cnt = rd[k * CNT_STRIDE + CNT_PAIRS];
+        const unsigned long long P = std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], M[k].partial_cap);
+        part_at[k + 1] = part_at[k] + (std::min(cnt, M[k].capacity) ? (size_t)P : 0u);
+    }
+    if (part_at[n]) {
+        if (S.h_partials_n < 2 * part_at[n]) {
+            if (S.h_partials) (void)hipHostFree(S.h_partials);
+            S.h_partials = nullptr;
+            S.h_partials_n = 0;
+            const size_t want = 2 * part_at[n] + part_at[n] / 2;   // some headroom
+            if ((e = hipHostMalloc((void**)&S.h_partials, want * sizeof(unsigned long long), hipHostMallocDefault)) !=
+                hipSuccess)
+                return hip_fail(e, "pinned partial-chunk copy");
+            S.h_partials_n = want;
+        }
+        for (size_t k = 0; k < n; ++k) {
+            const size_t P = part_at[k + 1] - part_at[k];
+            if (!P) continue;
+            const unsigned long long* src = static_cast<const unsigned long long*>(S.partials.p) + 2 * M[k].partial_off;
+            if ((e = hipMemcpyAsync(S.h_partials + 2 * part_at[k], src, 2 * P * sizeof(unsigned long long),
+                                    hipMemcpyDeviceToHost, stream)) != hipSuccess)
+                return hip_fail(e, "read partial chunks");
+        }
+        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "read partial chunks");
+    }
     for (size_t k = 0; k < n; ++k) {
         const unsigned long long cnt = rd[k * CNT_STRIDE + CNT_PAIRS];
         const unsigned long long K = rd[k * CNT_STRIDE + CNT_CHUNKS];
@@ -342,60 +410,9 @@ hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weig
         const unsigned long long cap = m.capacity;
         const unsigned long long target = std::min(cnt, cap);
         if (target == 0) continue;
-        const unsigned long long C = 1ull << m.chunk_shift;
-        const unsigned long long limit = cap + m.slack;   // stored positions are below this
-        // partly filled chunks (sorted by chunk)
-        std::vector<std::pair<unsigned long long, unsigned long long>> part(P);
-        if (P) {
-            S.h_partials.resize(2 * P);
-            const unsigned long long* src = static_cast<const unsigned long long*>(S.partials.p) + 2 * m.partial_off;
-            if ((e = hipMemcpyAsync(S.h_partials.data(), src, 2 * P * sizeof(unsigned long long),
-                                    hipMemcpyDeviceToHost, stream)) != hipSuccess ||
-                (e = hipStreamSynchronize(stream)) != hipSuccess)
-                return hip_fail(e, "read partial chunks");
-            for (unsigned long long q = 0; q < P; ++q) part[q] = {S.h_partials[2 * q], S.h_partials[2 * q + 1]};
-            std::sort(part.begin(), part.end());
-        }
-        // holes below the target length
-        std::vector<std::pair<unsigned long long, unsigned long long>> holes, data;
-        for (auto& pc : part) {
-            const unsigned long long lo = pc.first * C + pc.second;
-            const unsigned long long hi = std::min((pc.first + 1) * C, target);
-            if (lo < hi) holes.push_back({lo, hi});
-        }
-        // stored pairs at or past the target length
-        size_t pi = 0;
-        for (unsigned long long c = target / C; c < K && c * C < limit; ++c) {
-            while (pi < part.size() && part[pi].first < c) ++pi;
-            const unsigned long long fill = (pi < part.size() && part[pi].first == c) ? part[pi].second : C;
-            const unsigned long long lo = std::max(c * C, target);
-            const unsigned long long hi = std::min(c * C + fill, limit);
-            // positions below the capacity are in the caller's slice, the
-            // rest in the slack area: a chunk that straddles the capacity
-            // gives two segments
-            if (lo < std::min(hi, cap)) data.push_back({lo, std::min(hi, cap)});
-            if (std::max(lo, cap) < hi) data.push_back({std::max(lo, cap), hi});
-        }
-        unsigned long long unfilled = 0;
-        size_t hi_ = 0, di = 0;
-        unsigned long long hpos = holes.empty() ? 0 : holes[0].first;
-        unsigned long long dpos = data.empty() ? 0 : data[0].first;
-        while (hi_ < holes.size()) {
-            if (di >= data.size()) {
-                unfilled += holes[hi_].second - hpos;
-                if (++hi_ < holes.size()) hpos = holes[hi_].first;
-                continue;
-            }
-            const unsigned long long len = std::min(holes[hi_].second - hpos, data[di].second - dpos);
-            const unsigned long long src = dpos < cap ? m.out_offset + dpos : (kSlackFlag | (m.slack_off + dpos - cap));
-            S.h_segments.push_back(src);
-            S.h_segments.push_back(m.out_offset + hpos);
-            S.h_segments.push_back(len);
-            hpos += len;
-            dpos += len;
-            if (hpos == holes[hi_].second && ++hi_ < holes.size()) hpos = holes[hi_].first;
-            if (dpos == data[di].second && ++di < data.size()) dpos = data[di].first;
-        }
+        const unsigned long long unfilled =
+            plan_compaction(target, K, m.chunk_shift, cap, m.slack, S.h_partials + 2 * part_at[k], P,
+                            m.out_offset, m.slack_off, S.h_fill, S.h_segments);
         S.stored[k] = target - unfilled;
         if (unfilled) S.error |= ERR_UNFILLED;   // pairs lost: never expected
     }

@@ -71,6 +71,7 @@ struct TravArgs {
     const uint32_t* task_begin;   // n_items + 1 prefix of tasks per item
     uint32_t n_items, n_tasks;
     uint32_t* queues;             // kQueues work-queue heads, kQueueStride words apart
+    uint32_t queue_begin[9];      // queue q owns tasks [queue_begin[q], queue_begin[q + 1])
     const uint32_t* tile;         // 64 x 64 shifts
     unsigned long long* spill;    // per-wave spill stacks (uint2 entries)
     uint32_t spill_cap;           // entries per wave
@@ -84,11 +85,13 @@ struct TravArgs {
 constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr uint32_t kMaxItemsPerLaunch = 1024;
-// One work queue per XCD: queue q owns tasks [q T / 8, (q+1) T / 8); blocks
-// are dispatched to the 8 XCDs round-robin, so block b starts on queue b % 8
-// and its L2 sees a contiguous (spatially ordered) slice of the eyes.
+// One work queue per XCD: queue q owns a contiguous slice of the task list
+// (TravArgs::queue_begin); blocks are dispatched to the 8 XCDs round-robin,
+// so block b starts on queue b % 8 and its L2 sees a contiguous (spatially
+// ordered) slice of the eyes.
 constexpr uint32_t kQueues = 8;
 constexpr uint32_t kQueueStride = 32;   // 128 bytes between queue heads
+static_assert(sizeof(TravArgs::queue_begin) == (kQueues + 1) * sizeof(uint32_t), "one slice per queue");
 // Eye ordering: counting sort over (item, Morton cell) buckets.
 constexpr uint32_t kOrderMaxBuckets = 1u << 20;
 constexpr uint32_t kMinChunkShift = 7;  // a chunk holds >= 128 pairs (one emission step)

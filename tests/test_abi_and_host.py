@@ -297,3 +297,108 @@ def test_server_arena_is_first_fit_and_coalesces(arena_harness, seed):
     used, peak, largest, nblocks = map(int, out[len(expect)].split())
     assert used == 0 and nblocks == 1 and largest == size // 256 * 256
     assert peak == model.peak * 256
+
+
+COMPACT_HARNESS = r"""
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <set>
+#include <vector>
+#include "hrr_compact.hpp"
+// Simulates the kernel's chunked emission by W virtual waves (each leaving the
+// item `leaves` times), then applies the planned moves and checks the result.
+// args: count capacity shift waves leaves seed
+int main(int argc, char** argv) {
+    const unsigned long long count = strtoull(argv[1], 0, 10), cap = strtoull(argv[2], 0, 10);
+    const unsigned shift = atoi(argv[3]);
+    const unsigned waves = atoi(argv[4]), leaves = atoi(argv[5]);
+    std::mt19937_64 rng(strtoull(argv[6], 0, 10));
+    const unsigned long long C = 1ull << shift;
+    const unsigned long long pcap = (unsigned long long)waves * leaves;
+    const unsigned long long slack = cap ? 2 * pcap * C : 0;
+    std::vector<long long> buf(cap, -1), sl(slack, -1);
+    // split the pairs into (wave, visit) runs, then into bursts of <= 128
+    std::vector<std::vector<unsigned long long>> runs(pcap);
+    for (unsigned long long p = 0; p < count; ++p) runs[rng() % pcap].push_back(p);
+    struct W { long long chunk = -1; unsigned long long fill = 0; size_t run = 0, at = 0; };
+    std::vector<W> ws(waves);
+    for (unsigned w = 0; w < waves; ++w) ws[w].run = w * leaves;
+    unsigned long long K = 0;
+    std::vector<unsigned long long> partials;
+    auto store = [&](unsigned long long pos, unsigned long long id) {
+        if (pos < cap) buf[pos] = (long long)id;
+        else if (pos - cap < slack) sl[pos - cap] = (long long)id;
+    };
+    std::vector<unsigned> live;
+    for (unsigned w = 0; w < waves; ++w) live.push_back(w);
+    while (!live.empty()) {
+        const size_t li = rng() % live.size();
+        W& x = ws[live[li]];
+        std::vector<unsigned long long>& r = runs[x.run];
+        if (x.at >= r.size()) {   // leave the item: publish the partial chunk
+            if (x.chunk >= 0 && x.fill > 0) { partials.push_back(x.chunk); partials.push_back(x.fill); }
+            x.chunk = -1; x.fill = 0; x.at = 0;
+            if (++x.run % leaves == 0) { live.erase(live.begin() + li); }
+            continue;
+        }
+        const unsigned long long b = std::min<unsigned long long>(1 + rng() % 128, r.size() - x.at);
+        if (cap == 0) { x.at += b; continue; }
+        if (x.chunk < 0) { x.chunk = (long long)K++; x.fill = 0; }
+        long long next = -1;
+        if (x.fill + b > C) next = (long long)K++;
+        for (unsigned long long q = 0; q < b; ++q) {
+            const unsigned long long pos = x.fill + q;
+            store(pos < C ? x.chunk * C + pos : next * C + (pos - C), r[x.at + q]);
+        }
+        x.at += b;
+        x.fill += b;
+        if (x.fill >= C) { x.fill -= C; x.chunk = next; if (x.fill == 0) x.chunk = -1; }
+    }
+    const unsigned long long target = std::min(count, cap);
+    std::vector<unsigned long long> fill, seg;
+    const unsigned long long unfilled = hrr::plan_compaction(target, K, shift, cap, slack, partials.data(),
+                                                             partials.size() / 2, 0, 0, fill, seg);
+    // moves read sources that are never destinations, so order does not matter
+    for (size_t s = 0; s < seg.size(); s += 3) {
+        const unsigned long long src = seg[s], dst = seg[s + 1], len = seg[s + 2];
+        for (unsigned long long q = 0; q < len; ++q)
+            buf[dst + q] = (src & hrr::kSlackFlag) ? sl[(src & ~hrr::kSlackFlag) + q] : buf[src + q];
+    }
+    std::set<long long> seen;
+    for (unsigned long long p = 0; p < target; ++p) {
+        if (buf[p] < 0 || buf[p] >= (long long)count || !seen.insert(buf[p]).second) {
+            printf("bad position %llu (value %lld)\n", p, buf[p]);
+            return 1;
+        }
+    }
+    printf("ok unfilled=%llu segments=%zu partials=%zu chunks=%llu\n", unfilled, seg.size() / 3, partials.size() / 2, K);
+    return unfilled ? 1 : 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def compact_harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("compact")
+    src = d / "compact.cpp"
+    src.write_text(COMPACT_HARNESS)
+    exe = d / "compact"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+@pytest.mark.parametrize("count,extra,shift,waves,leaves", [
+    (0, 10, 7, 4, 1), (1, 0, 7, 4, 1), (1000, 0, 7, 16, 1), (1000, 1, 7, 16, 1),
+    (1000, 77, 7, 16, 2), (5000, 5000, 8, 64, 2), (20000, 0, 9, 200, 2), (20000, 300, 7, 300, 1),
+    (3000, -1000, 7, 40, 2), (3000, -2999, 7, 40, 1), (100000, -50000, 10, 512, 2),
+    (100000, 12345, 13, 512, 2), (70000, 0, 13, 3, 2)])
+def test_output_compaction_fills_every_position(compact_harness, count, extra, shift, waves, leaves):
+    """The plan for making an item's output dense, against a simulation of the
+    kernel's chunked emission (random interleaving of waves, capacity above,
+    equal to and below the count, one or two departures per wave)."""
+    cap = count + extra
+    for seed in range(3):
+        r = subprocess.run([compact_harness, str(count), str(cap), str(shift), str(waves), str(leaves),
+                            str(seed)], capture_output=True, text=True)
+        assert r.returncode == 0, r.stdout + r.stderr
