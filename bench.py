@@ -63,6 +63,14 @@ def frame_workload(args):
     t0 = time.time()
     h = ctx.build_hierarchy(fr["lights"], leaf_size=fr["leaf"])
     build_s = time.time() - t0
+    lights_dev = torch.from_numpy(fr["lights"]).to("cuda:0")
+    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"])   # warm-up (allocations, code load)
+    hd.free()
+    _sync_all()
+    t0 = time.perf_counter()
+    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"])
+    build_dev_s = time.perf_counter() - t0
+    hd.free()
     eyes = torch.from_numpy(fr["eyes"]).to("cuda:0")
     n_eyes = fr["eyes"].shape[0]
     method = RMQ_METHODS[args.rmq]
@@ -117,6 +125,7 @@ def frame_workload(args):
         "kernel_ms": gpu_ms,
         "step_gpu_ms": step_gpu_ms,
         "hierarchy_build_s": build_s,
+        "hierarchy_build_device_s": build_dev_s,
         "units": {"node_visits": st["node_visits"], "rmq_calls": st["rmq_calls"],
                   "leaf_tests": st["leaf_tests"], "pairs": n},
         "algorithmic_lane_ops": ops,

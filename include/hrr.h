@@ -138,7 +138,25 @@ typedef struct hrr_hierarchy_info {
 hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz,
                                uint32_t n_lights, uint32_t leaf_size,
                                const float* box, hrr_hierarchy** out);
+/* The same hierarchy built on the GPU (the step before the path, for light
+ * caches that already live in device memory): lights_xyz_dev is device
+ * memory, 3*n_lights fp32; box and leaf_size as above.  The result is the
+ * one hrr_build_hierarchy returns for the same lights, record for record
+ * (same order, splits, exact boxes and preorder numbering): Morton codes,
+ * a stable radix sort, one launch per tree level for the splits, then a
+ * bottom-up refit.  Work is ordered on `stream`; the call returns when the
+ * hierarchy is complete.  Non-finite coordinates return HRR_E_INVALID. */
+hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* lights_xyz_dev,
+                                      uint32_t n_lights, uint32_t leaf_size,
+                                      const float* box, void* stream, hrr_hierarchy** out);
 hrr_status hrr_hierarchy_get_info(const hrr_hierarchy* h, hrr_hierarchy_info* out);
+/* nodes_out (host, 64 bytes per internal node): the node records in preorder.
+ * Each holds the left child's box (lo xyz, then its first index a), the right
+ * child's box (hi xyz of the left box, then the split c; lo xyz of the right
+ * box, then the end b; hi xyz of the right box, then the right child's record
+ * number or 0xFFFFFFFF for a leaf).  The left child, when internal, is the
+ * next record. */
+hrr_status hrr_hierarchy_records(const hrr_hierarchy* h, void* nodes_out);
 /* perm_out (host u32[n_lights]): perm_out[i] = original index of the light
  * with sequence index i. */
 hrr_status hrr_hierarchy_permutation(const hrr_hierarchy* h, uint32_t* perm_out);

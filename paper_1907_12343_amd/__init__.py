@@ -97,7 +97,9 @@ SIGNATURES = {
     "hrr_version": (_i32, []),
     "hrr_range_min": (_i32, [_P, _P, _P, _P, _u64, _u32, _P, _P, _P, _P]),
     "hrr_build_hierarchy": (_i32, [_P, _P, _u32, _u32, _P, _P]),
+    "hrr_build_hierarchy_device": (_i32, [_P, _P, _u32, _u32, _P, _P, _P]),
     "hrr_hierarchy_get_info": (_i32, [_P, _P]),
+    "hrr_hierarchy_records": (_i32, [_P, _P]),
     "hrr_hierarchy_permutation": (_i32, [_P, _P]),
     "hrr_hierarchy_sorted_lights": (_i32, [_P, _P]),
     "hrr_free_hierarchy": (None, [_P, _P]),
@@ -182,6 +184,10 @@ def u32_tensor(a, device):
     return torch.from_numpy(arr).to(device)
 
 
+NODE_DTYPE = np.dtype([("lo_l", "<f4", 3), ("a", "<u4"), ("hi_l", "<f4", 3), ("c", "<u4"),
+                       ("lo_r", "<f4", 3), ("b", "<u4"), ("hi_r", "<f4", 3), ("right", "<u4")])
+
+
 class Hierarchy:
     """A light hierarchy resident on the context's device."""
 
@@ -207,6 +213,12 @@ class Hierarchy:
         out = np.empty((self.n_lights, 3), np.float32)
         _check(_lib.hrr_hierarchy_sorted_lights(self.handle, out.ctypes.data_as(_P)),
                "sorted lights")
+        return out
+
+    def records(self) -> np.ndarray:
+        """Node records in preorder as a structured array (see include/hrr.h)."""
+        out = np.zeros(self.n_nodes, NODE_DTYPE)
+        _check(_lib.hrr_hierarchy_records(self.handle, out.ctypes.data_as(_P)), "hierarchy records")
         return out
 
     def free(self):
@@ -288,6 +300,20 @@ class Context:
         _check(_lib.hrr_build_hierarchy(self.handle, lights.ctypes.data_as(_P), lights.shape[0],
                                         leaf_size, None if bx is None else bx.ctypes.data_as(_P),
                                         ctypes.byref(h)), "hrr_build_hierarchy")
+        return Hierarchy(self, h.value)
+
+    def build_hierarchy_device(self, lights_xyz, leaf_size: int = 1, box=None, stream=None) -> Hierarchy:
+        """The same hierarchy built on the GPU from a (n, 3) float32 cuda tensor."""
+        import torch
+        if not (lights_xyz.is_cuda and lights_xyz.dtype == torch.float32 and lights_xyz.is_contiguous()
+                and lights_xyz.dim() == 2 and lights_xyz.shape[1] == 3):
+            raise ValueError("lights must be a contiguous (n, 3) float32 cuda tensor")
+        bx = None if box is None else np.ascontiguousarray(box, dtype=np.float32)
+        h = _P()
+        _check(_lib.hrr_build_hierarchy_device(self.handle, _dptr(lights_xyz), lights_xyz.shape[0],
+                                               leaf_size, None if bx is None else bx.ctypes.data_as(_P),
+                                               _stream_handle(stream), ctypes.byref(h)),
+               "hrr_build_hierarchy_device")
         return Hierarchy(self, h.value)
 
     # -- traversal ------------------------------------------------------------

@@ -30,6 +30,8 @@ SOURCES = [
     ("hrr_launch.cpp", HOST),
     ("hrr_build.cpp", HOST),
     ("hrr_serve.cpp", HOST),
+    ("hrr_build_device.hip", DEVICE),
+    ("hrr_build_device_host.cpp", HOST),
 ]
 
 

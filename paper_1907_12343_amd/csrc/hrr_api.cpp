@@ -290,15 +290,46 @@ HRR_EXPORT hrr_status hrr_hierarchy_get_info(const hrr_hierarchy* h, hrr_hierarc
     return HRR_OK;
 }
 
+// Host copies of a device-built hierarchy's order and sorted positions.
+static hrr_status ensure_host_copies(const hrr_hierarchy* h) {
+    if (h->host_copies) return HRR_OK;
+    hipError_t e = hipSetDevice(h->owner->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t n = h->n_lights;
+    std::vector<float> l4(4 * n);
+    h->perm.resize(n);
+    if (n && ((e = hipMemcpy(h->perm.data(), h->d_perm, n * sizeof(uint32_t), hipMemcpyDeviceToHost)) != hipSuccess ||
+              (e = hipMemcpy(l4.data(), h->d_lights, 4 * n * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess))
+        return hip_fail(e, "hierarchy download");
+    h->sorted_xyz.resize(3 * n);
+    for (size_t i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) h->sorted_xyz[3 * i + k] = l4[4 * i + k];
+    h->host_copies = true;
+    return HRR_OK;
+}
+
 HRR_EXPORT hrr_status hrr_hierarchy_permutation(const hrr_hierarchy* h, uint32_t* perm_out) {
     if (!h || (!perm_out && h->n_lights)) return fail(HRR_E_INVALID, "hrr_hierarchy_permutation: null argument");
+    hrr_status st = ensure_host_copies(h);
+    if (st != HRR_OK) return st;
     if (h->n_lights) memcpy(perm_out, h->perm.data(), h->n_lights * sizeof(uint32_t));
     return HRR_OK;
 }
 
 HRR_EXPORT hrr_status hrr_hierarchy_sorted_lights(const hrr_hierarchy* h, float* sorted_xyz_out) {
     if (!h || (!sorted_xyz_out && h->n_lights)) return fail(HRR_E_INVALID, "hrr_hierarchy_sorted_lights: null argument");
+    hrr_status st = ensure_host_copies(h);
+    if (st != HRR_OK) return st;
     if (h->n_lights) memcpy(sorted_xyz_out, h->sorted_xyz.data(), 3 * (size_t)h->n_lights * sizeof(float));
+    return HRR_OK;
+}
+
+HRR_EXPORT hrr_status hrr_hierarchy_records(const hrr_hierarchy* h, void* nodes_out) {
+    if (!h || (!nodes_out && h->n_nodes)) return fail(HRR_E_INVALID, "hrr_hierarchy_records: null argument");
+    if (!h->n_nodes) return HRR_OK;
+    hipError_t e = hipSetDevice(h->owner->device);
+    if (e == hipSuccess) e = hipMemcpy(nodes_out, h->d_nodes, (size_t)h->n_nodes * sizeof(Node), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hierarchy records download");
     return HRR_OK;
 }
 

@@ -20,8 +20,10 @@ struct hrr_hierarchy {
     hrr::Node* d_nodes = nullptr;
     float* d_lights = nullptr;       // float4 per light
     uint32_t* d_perm = nullptr;
-    std::vector<uint32_t> perm;      // host copy
-    std::vector<float> sorted_xyz;   // host copy
+    // host copies (filled on demand for hierarchies built on the device)
+    mutable std::vector<uint32_t> perm;
+    mutable std::vector<float> sorted_xyz;
+    mutable bool host_copies = true;
     uint64_t device_bytes = 0;
 };
 
