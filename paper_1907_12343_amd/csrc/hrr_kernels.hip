@@ -883,8 +883,13 @@ extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const
     if (n == 0) return hipSuccess;
     const int vec = ((((uintptr_t)a) | ((uintptr_t)b) | ((uintptr_t)r) | ((uintptr_t)k) | ((uintptr_t)v)) & 15u) == 0;
     const uint64_t work = vec ? (n + 3) / 4 : n;
+    // One 4-query group per thread: a grid far larger than the resident
+    // capacity keeps the most loads in flight (measured 1.26 ms with 16
+    // blocks per CU and a grid-stride loop, 1.04 ms with one group per
+    // thread for 2^28 queries).  The loop still covers grids above the cap.
     uint64_t blocks = (work + 255) / 256;
-    const uint64_t max_blocks = (uint64_t)(n_cu > 0 ? n_cu : 256) * 16;
+    const uint64_t max_blocks = 1ull << 30;
+    (void)n_cu;
     if (blocks > max_blocks) blocks = max_blocks;
     if (blocks < 1) blocks = 1;
     if (method == 1)
