@@ -141,6 +141,7 @@ def frame_workload(args):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traverse_frame_traffic.json")
+RMQ_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "range_min_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1907_12343_amd", "csrc", f)
                   for f in ("hrr_kernels.hip", "hrr_rmq.hpp", "hrr_types.hpp")]
 
@@ -154,15 +155,16 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def _traffic_bytes(args):
-    """HBM bytes of one timed traversal launch: FETCH_SIZE + WRITE_SIZE from
-    rocprofv3 --pmc runs, scaled by the copy-kernel calibration, as recorded in
-    profiles/ together with the digest of the kernel sources they were taken
-    on; None when the kernel has changed since (or --traffic-kib overrides)."""
+def _traffic_bytes(args, path=TRAFFIC_FILE):
+    """HBM bytes of one timed launch of the dominant kernel: FETCH_SIZE +
+    WRITE_SIZE from rocprofv3 --pmc runs, scaled by the copy-kernel
+    calibration, as recorded in profiles/ together with the digest of the
+    kernel sources they were taken on; None when the kernel has changed since
+    (or --traffic-kib overrides)."""
     if args.traffic_kib is not None:
         return (args.traffic_kib[0] + args.traffic_kib[1]) * 1024.0
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -224,7 +226,7 @@ def rangemin_workload(args):
                    "rmq": args.rmq},
         "kernel_ms": gpu_ms,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_bytes(args, RMQ_TRAFFIC_FILE)},
     }
     if not args.no_cpu_baseline:
         import oracle
