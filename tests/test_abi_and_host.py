@@ -402,3 +402,76 @@ def test_output_compaction_fills_every_position(compact_harness, count, extra, s
         r = subprocess.run([compact_harness, str(count), str(cap), str(shift), str(waves), str(leaves),
                             str(seed)], capture_output=True, text=True)
         assert r.returncode == 0, r.stdout + r.stderr
+
+
+RMQ_HARNESS = r"""
+#include <cstdio>
+#include "hrr_rmq.hpp"
+// stdin: n, then n lines "a b R"; stdout per query: argmin of each method 0..3
+int main() {
+    unsigned n;
+    if (scanf("%u", &n) != 1) return 2;
+    for (unsigned q = 0; q < n; ++q) {
+        unsigned a, b, R;
+        if (scanf("%u %u %u", &a, &b, &R) != 3) return 3;
+        const unsigned kr = hrr::threshold_index(R);
+        printf("%u %u %u %u\n", hrr::rmq<0>(a, b, kr), hrr::rmq<1>(a, b, kr), hrr::rmq<2>(a, b, kr),
+               hrr::rmq<3>(a, b, kr));
+    }
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def rmq_harness(tmp_path_factory):
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("clang++ with __builtin_bitreverse32 is not available")
+    d = tmp_path_factory.mktemp("rmq")
+    src = d / "rmq.cpp"
+    src.write_text(RMQ_HARNESS)
+    exe = d / "rmq"
+    subprocess.run([clang, "-O2", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+def test_device_range_minimum_code_on_the_host(orc, rmq_harness):
+    """The range-minimum functions the kernels run (host-compiled) against the
+    oracle's scan: random ranges of every length class, node-like aligned
+    ranges, ranges at both ends of the index space, shifts 0 / 2^31 / 2^32-1
+    and shifts that put k_r just inside, at and just outside the range."""
+    rng = np.random.default_rng(77)
+    qs = []
+    for t in range(6000):
+        L = int(2 ** rng.uniform(0, 12))
+        mode = t % 6
+        if mode == 0:
+            a = int(rng.integers(0, 64))
+        elif mode == 1:
+            a = (1 << 32) - 1 - L - int(rng.integers(0, 64))
+        elif mode == 2:
+            a = int(rng.integers(0, 1 << 20)) // L * L      # node-like, aligned
+        else:
+            a = int(rng.integers(0, (1 << 32) - 1 - L))
+        b = a + L
+        R = int(rng.integers(0, 1 << 32))
+        if t % 7 == 0:
+            R = 0
+        elif t % 11 == 0:
+            R = (1 << 32) - 1
+        elif t % 13 == 0:
+            R = 1 << 31
+        elif t % 17 == 0:      # k_r at a - 1, a .. b - 1 or b
+            k = (a - 1 + int(rng.integers(0, L + 2))) & 0xFFFFFFFF
+            R = (-int(orc.bitrev(k))) & 0xFFFFFFFF
+        qs.append((a, b, R))
+    a = np.array([q[0] for q in qs], np.uint32)
+    b = np.array([q[1] for q in qs], np.uint32)
+    r = np.array([q[2] for q in qs], np.uint32)
+    inp = "%d\n" % len(qs) + "\n".join("%d %d %d" % q for q in qs) + "\n"
+    out = subprocess.run([rmq_harness], input=inp, capture_output=True, text=True, check=True).stdout
+    got = np.array([[int(x) for x in ln.split()] for ln in out.splitlines()], np.uint64)
+    want, _ = orc.rmq_scan(a, b, r)
+    for m in range(4):
+        assert np.array_equal(got[:, m], want.astype(np.uint64)), "method %d" % m
