@@ -133,6 +133,12 @@ def frame_workload(args):
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
                      "traffic": _traffic_bytes(args)},
     }
+    traffic = line["roofline"]["traffic"]
+    if traffic is not None:
+        # everything that leaves the L2s (Infinity Cache hits included): the
+        # walk is bound by this miss stream, not by VALU issue
+        line["memory_side"] = {"bytes": traffic, "TB_per_s": traffic / (gpu_ms * 1e-3) / 1e12,
+                               "frac_of_hbm_peak": traffic / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_frame(fr, n_eyes, args)
     h.free()
@@ -227,6 +233,9 @@ def rangemin_workload(args):
         "kernel_ms": gpu_ms,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_bytes(args, RMQ_TRAFFIC_FILE)},
+        # the integer work beside it: about OPS_RMQ lane-operations per query
+        "valu": {"lane_ops": nq * OPS_RMQ,
+                 "frac": nq * OPS_RMQ / (gpu_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
     }
     if not args.no_cpu_baseline:
         import oracle
