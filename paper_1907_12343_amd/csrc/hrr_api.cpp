@@ -82,6 +82,7 @@ void release_scratch(LaunchScratch& S) {
     S.misc.release();
     S.spill.release();
     S.partials.release();
+    S.packed.release();
     S.slack_pairs.release();
     S.slack_weights.release();
     S.segments.release();
@@ -193,6 +194,14 @@ HRR_EXPORT hrr_status hrr_create(int device, const uint32_t* tile, hrr_ctx** out
         (void)hipFree(c->d_tile);
         delete c;
         return hip_fail(e, "tile upload");
+    }
+    // Common trailing zeros and significant bits of the tile's values: the
+    // eye ordering groups eyes by the low significant bits of their shift.
+    uint32_t all = 0;
+    for (int q = 0; q < 4096; ++q) all |= tile[q];
+    if (all) {
+        c->tile_tz = (uint32_t)__builtin_ctz(all);
+        c->tile_bits = 32u - (uint32_t)__builtin_clz(all) - c->tile_tz;
     }
     *out = c;
     return HRR_OK;

@@ -22,18 +22,23 @@ namespace hrr {
 // Source offsets with this bit set are slack-area offsets.
 constexpr unsigned long long kSlackFlag = 1ull << 63;
 
+// Reusable scratch of plan_compaction (keeps its capacity between calls).
+struct CompactScratch {
+    std::vector<unsigned long long> fill;
+    std::vector<std::pair<unsigned long long, unsigned long long>> holes, data;
+};
+
 // Appends (source, destination, length) triples to `segments` (sources are
 // out_offset + position, or kSlackFlag | (slack_off + position - capacity);
 // destinations out_offset + position) and returns the number of positions
 // below `target` left unfilled (0 whenever the slack holds twice the chunks
 // of all partial chunks).  partials: n_partials (chunk, fill) pairs in any
-// order; chunks: the number of chunks handed out; `fill` is scratch.
+// order; chunks: the number of chunks handed out.
 inline unsigned long long plan_compaction(unsigned long long target, unsigned long long chunks, uint32_t shift,
                                           unsigned long long capacity, unsigned long long slack,
                                           const unsigned long long* partials, unsigned long long n_partials,
                                           unsigned long long out_offset, unsigned long long slack_off,
-                                          std::vector<unsigned long long>& fill,
-                                          std::vector<unsigned long long>& segments) {
+                                          CompactScratch& scratch, std::vector<unsigned long long>& segments) {
     if (target == 0) return 0;
     const unsigned long long C = 1ull << shift;
     const unsigned long long limit = capacity + slack;   // stored positions are below this
@@ -41,7 +46,11 @@ inline unsigned long long plan_compaction(unsigned long long target, unsigned lo
     // c0 = target / C .. up to the limit (at most n_partials + 1 of them when
     // the count fits), full except the partly filled ones.  Holes and data
     // pair up in any order, so nothing is sorted.
-    std::vector<std::pair<unsigned long long, unsigned long long>> holes, data;
+    std::vector<unsigned long long>& fill = scratch.fill;
+    std::vector<std::pair<unsigned long long, unsigned long long>>& holes = scratch.holes;
+    std::vector<std::pair<unsigned long long, unsigned long long>>& data = scratch.data;
+    holes.clear();
+    data.clear();
     const unsigned long long c0 = target / C;
     const unsigned long long c_end = std::min<unsigned long long>(chunks, (limit + C - 1) / C);
     fill.assign(c_end > c0 ? (size_t)(c_end - c0) : 0u, C);

@@ -11,6 +11,7 @@
 
 #include "../../include/hrr.h"
 #include "hrr_build.hpp"
+#include "hrr_compact.hpp"
 #include "hrr_types.hpp"
 
 struct hrr_hierarchy {
@@ -66,7 +67,7 @@ struct ItemMeta {
 // Per-launch device scratch: one set per stream slot so that concurrent
 // launches (the server) never share queue heads or counters.
 struct LaunchScratch {
-    DevBuf items, task_begin, counters, misc, spill, partials, slack_pairs, slack_weights, segments;
+    DevBuf items, task_begin, counters, misc, spill, partials, packed, slack_pairs, slack_weights, segments;
     DevBuf order_keys, order_idx, order_hist, order_items, order_vbegin, queues;
     std::vector<ItemDesc> h_items;
     std::vector<uint32_t> h_task_begin;
@@ -76,7 +77,7 @@ struct LaunchScratch {
     unsigned long long* h_partials = nullptr;         // pinned host copy for hole filling
     size_t h_partials_n = 0;
     std::vector<unsigned long long> h_segments;
-    std::vector<unsigned long long> h_fill;           // fill of the chunks past an item's length
+    CompactScratch compact;                           // scratch of the compaction plan
     std::vector<ItemMeta> meta;
     size_t n_items = 0;
     bool with_weights = false;
@@ -99,6 +100,7 @@ struct hrr_ctx {
     int device = 0;
     int n_cu = 256;
     uint32_t* d_tile = nullptr;
+    uint32_t tile_tz = 32, tile_bits = 0;   // shared trailing zeros / significant bits of the tile values
     hrr::LaunchScratch scratch;   // scratch of the synchronous entry points
     std::mutex tune_mu;
     std::map<hrr::TuneKey, hrr::TuneVal> tune;

@@ -763,14 +763,19 @@ void traverse_kernel(TravArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// eye ordering: counting sort of the virtual eyes by (item, Morton cell)
+// eye ordering: counting sort of the virtual eyes by (item, Morton cell, shift class)
 // ---------------------------------------------------------------------------
 //
 // The traversal result does not depend on the order in which eyes are
 // processed; processing spatially close eyes together lets an XCD's L2 hold
 // the part of the hierarchy they share.  Cells: `bits` bits per axis of the
-// eye position inside the item's light box, interleaved x-y-z; the bucket of
-// virtual eye g of item k is (k << 3 bits) | cell.
+// eye position inside the item's light box, interleaved x-y-z.  Within a cell,
+// eyes are grouped by the shift class: the low `rbits` significant bits of the
+// eye's tile value t (t = m * 2^tz), bit reversed.  The minimum over an aligned
+// block of 2^s indices is (bitreverse(p) + r) mod 2^(32-s), so two eyes whose
+// m agree modulo 2^q see equal minima on every block with s >= 32 - tz - q;
+// such eyes visit nearly the same nodes.  Bucket of virtual eye g of item k:
+// ((k << 3 bits | cell) << rbits) | class.
 
 __device__ __forceinline__ uint32_t spread3_10(uint32_t v) {
     v &= 0x3FFu;
@@ -791,8 +796,9 @@ __device__ __forceinline__ uint32_t cell_of(float x, float lo, float scale, uint
 
 __global__ __launch_bounds__(256) void order_keys_kernel(const OrderItem* __restrict__ items,
                                                          const uint32_t* __restrict__ vbegin, uint32_t n_items,
-                                                         uint32_t total, uint32_t bits, uint32_t* __restrict__ keys,
-                                                         uint32_t* __restrict__ hist) {
+                                                         uint32_t total, uint32_t bits, uint32_t rbits,
+                                                         const uint32_t* __restrict__ tile, uint32_t tile_tz,
+                                                         uint32_t* __restrict__ keys, uint32_t* __restrict__ hist) {
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
         uint32_t lo = 0, hi = n_items;
         while (hi - lo > 1) {
@@ -806,45 +812,129 @@ __global__ __launch_bounds__(256) void order_keys_kernel(const OrderItem* __rest
         const uint32_t cx = cell_of(e[0], I.lo[0], I.scale[0], bits);
         const uint32_t cy = cell_of(e[1], I.lo[1], I.scale[1], bits);
         const uint32_t cz = cell_of(e[2], I.lo[2], I.scale[2], bits);
-        const uint32_t key = (lo << (3u * bits)) | (spread3_10(cx) << 2) | (spread3_10(cy) << 1) | spread3_10(cz);
+        uint32_t key = (lo << (3u * bits)) | (spread3_10(cx) << 2) | (spread3_10(cy) << 1) | spread3_10(cz);
+        if (rbits) {
+            const uint32_t pix = I.pixel_base + j;
+            const uint32_t x = pix % I.width;
+            const uint32_t y = pix / I.width;
+            const uint32_t t = tile[(x & 63u) * 64u + (y & 63u)];
+            key = (key << rbits) | (__brev(t >> tile_tz) >> (32u - rbits));
+        }
         keys[g] = key;
         atomicAdd(hist + key, 1u);
     }
 }
 
-// Exclusive prefix sum of n counts in place, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void exclusive_scan_kernel(uint32_t* __restrict__ v, uint32_t n) {
-    __shared__ uint32_t part[1024];
-    const uint32_t per = (n + 1023u) / 1024u;
-    const uint32_t b = threadIdx.x * per;
-    const uint32_t e = min(n, b + per);
-    uint32_t sum = 0;
-    for (uint32_t q = b; q < e; ++q) sum += v[q];
-    part[threadIdx.x] = sum;
+// Exclusive prefix sum of n counts in place, in three launches: every block
+// sums a chunk of kScanChunk counts, one block scans the chunk sums, and every
+// block rescans its chunk from its base.
+constexpr uint32_t kScanChunk = 4096;   // 16 counts per thread of 256
+constexpr uint32_t kScanMaxChunks = 1024;
+
+// Inclusive scan of one value per thread over a block of 256 (LDS, in order).
+__device__ __forceinline__ uint32_t block_inclusive_scan_256(uint32_t x, uint32_t* lds) {
+    const uint32_t t = threadIdx.x;
+    lds[t] = x;
     __syncthreads();
-    for (uint32_t off = 1; off < 1024u; off <<= 1) {
-        const uint32_t add = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+    for (uint32_t off = 1; off < 256u; off <<= 1) {
+        const uint32_t add = t >= off ? lds[t - off] : 0u;
         __syncthreads();
-        part[threadIdx.x] += add;
+        lds[t] += add;
         __syncthreads();
     }
-    uint32_t run = part[threadIdx.x] - sum;
-    for (uint32_t q = b; q < e; ++q) {
-        const uint32_t x = v[q];
-        v[q] = run;
-        run += x;
+    const uint32_t r = lds[t];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(256) void scan_chunk_sums_kernel(const uint32_t* __restrict__ v, uint32_t n,
+                                                              uint32_t* __restrict__ sums) {
+    __shared__ uint32_t lds[256];
+    const uint32_t b = blockIdx.x * kScanChunk + threadIdx.x * 16u;
+    uint32_t sum = 0;
+    for (uint32_t q = 0; q < 16u; ++q) sum += b + q < n ? v[b + q] : 0u;
+    const uint32_t incl = block_inclusive_scan_256(sum, lds);
+    if (threadIdx.x == 255u) sums[blockIdx.x] = incl;
+}
+
+__global__ __launch_bounds__(256) void scan_sums_kernel(uint32_t* __restrict__ sums, uint32_t n_chunks) {
+    __shared__ uint32_t lds[256];
+    const uint32_t b = threadIdx.x * 4u;
+    uint32_t x[4], sum = 0;
+    for (uint32_t q = 0; q < 4u; ++q) {
+        x[q] = b + q < n_chunks ? sums[b + q] : 0u;
+        sum += x[q];
+    }
+    uint32_t run = block_inclusive_scan_256(sum, lds) - sum;
+    for (uint32_t q = 0; q < 4u; ++q) {
+        if (b + q < n_chunks) sums[b + q] = run;
+        run += x[q];
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_apply_kernel(uint32_t* __restrict__ v, uint32_t n,
+                                                         const uint32_t* __restrict__ sums) {
+    __shared__ uint32_t lds[256];
+    const uint32_t b = blockIdx.x * kScanChunk + threadIdx.x * 16u;
+    uint32_t x[16], sum = 0;
+    for (uint32_t q = 0; q < 16u; ++q) {
+        x[q] = b + q < n ? v[b + q] : 0u;
+        sum += x[q];
+    }
+    uint32_t run = sums[blockIdx.x] + block_inclusive_scan_256(sum, lds) - sum;
+    for (uint32_t q = 0; q < 16u; ++q) {
+        if (b + q < n) v[b + q] = run;
+        run += x[q];
     }
 }
 
 __global__ __launch_bounds__(256) void order_scatter_kernel(const uint32_t* __restrict__ keys,
                                                             const uint32_t* __restrict__ vbegin, uint32_t total,
-                                                            uint32_t bits, uint32_t* __restrict__ offsets,
+                                                            uint32_t key_bits, uint32_t* __restrict__ offsets,
                                                             uint32_t* __restrict__ order) {
     for (uint32_t g = blockIdx.x * blockDim.x + threadIdx.x; g < total; g += gridDim.x * blockDim.x) {
         const uint32_t key = keys[g];
-        const uint32_t item = key >> (3u * bits);
+        const uint32_t item = key >> key_bits;
         const uint32_t pos = atomicAdd(offsets + key, 1u);
         order[pos] = g - vbegin[item];
+    }
+}
+
+// After a traversal: pack every item's list of partly filled chunks into
+// one array (items in the order of the item table), so that the host reads
+// all of them with a single copy.  An item's list counts only when it stored
+// pairs (min(count, capacity) > 0), as the host's compaction plan assumes;
+// the packed offset of item k goes to its counter line (CNT_PACKED).  One
+// block; n <= 1024 items.
+__global__ __launch_bounds__(1024) void pack_partials_kernel(const ItemDesc* __restrict__ items, uint32_t n,
+                                                             unsigned long long* __restrict__ packed) {
+    __shared__ unsigned long long cnt[1024], off[1024];
+    const uint32_t t = threadIdx.x;
+    unsigned long long P = 0;
+    if (t < n) {
+        const ItemDesc& D = items[t];
+        const unsigned long long pairs = D.counters[CNT_PAIRS];
+        const unsigned long long listed = D.counters[CNT_PARTIALS];
+        const unsigned long long cap = D.partial_cap;
+        P = (pairs < D.capacity ? pairs : D.capacity) ? (listed < cap ? listed : cap) : 0ull;
+    }
+    cnt[t] = P;
+    off[t] = P;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024u; d <<= 1) {
+        const unsigned long long add = t >= d ? off[t - d] : 0ull;
+        __syncthreads();
+        off[t] += add;
+        __syncthreads();
+    }
+    off[t] -= P;   // exclusive
+    if (t < n) items[t].counters[CNT_PACKED] = off[t];
+    __syncthreads();
+    for (uint32_t k = 0; k < n; ++k) {
+        const unsigned long long words = 2ull * cnt[k];
+        const unsigned long long* src = items[k].partials;
+        unsigned long long* dst = packed + 2ull * off[k];
+        for (unsigned long long q = t; q < words; q += 1024u) dst[q] = src[q];
     }
 }
 
@@ -900,6 +990,16 @@ extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const
         hipLaunchKernelGGL(hrr::rmq_kernel<3>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     else
         hipLaunchKernelGGL(hrr::rmq_kernel<0>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
+    return hipGetLastError();
+}
+
+// Pack the items' partial-chunk lists (see pack_partials_kernel); packed
+// must hold 2 words per partial-list entry of every item.
+extern "C" hipError_t hrr_launch_pack_partials(const hrr::ItemDesc* items, uint32_t n_items,
+                                               unsigned long long* packed, hipStream_t stream) {
+    if (n_items == 0) return hipSuccess;
+    if (n_items > 1024u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(hrr::pack_partials_kernel, dim3(1), dim3(1024), 0, stream, items, n_items, packed);
     return hipGetLastError();
 }
 
@@ -993,21 +1093,32 @@ extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t me
 }
 
 // Processing order of the virtual eyes of a launch (see order_keys_kernel).
-// hist must hold n_items << (3 bits) counters; keys and order `total` words.
+// hist must hold (n_items << (3 bits + rbits)) + 1024 counters (the last 1024
+// are the scan's chunk sums); keys and order `total` words; tile is the
+// context's 64x64 tile, whose values share tile_tz trailing zeros (rbits = 0
+// leaves the shift out of the key).
 extern "C" hipError_t hrr_launch_order(const hrr::OrderItem* items, const uint32_t* vbegin, uint32_t n_items,
-                                       uint32_t total, uint32_t bits, uint32_t* keys, uint32_t* hist, uint32_t* order,
-                                       int n_cu, hipStream_t stream) {
+                                       uint32_t total, uint32_t bits, uint32_t rbits, const uint32_t* tile,
+                                       uint32_t tile_tz, uint32_t* keys, uint32_t* hist, uint32_t* order, int n_cu,
+                                       hipStream_t stream) {
     if (total == 0) return hipSuccess;
-    const uint32_t n_buckets = n_items << (3u * bits);
+    if (rbits > 31u || (rbits && tile_tz > 31u)) return hipErrorInvalidValue;
+    const uint32_t key_bits = 3u * bits + rbits;
+    const uint32_t n_buckets = n_items << key_bits;
+    const uint32_t n_chunks = (n_buckets + hrr::kScanChunk - 1u) / hrr::kScanChunk;
+    if (n_chunks > hrr::kScanMaxChunks) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(hist, 0, (size_t)n_buckets * sizeof(uint32_t), stream);
     if (e != hipSuccess) return e;
     uint32_t blocks = (total + 255u) / 256u;
     const uint32_t max_blocks = (uint32_t)(n_cu > 0 ? n_cu : 256) * 8u;
     if (blocks > max_blocks) blocks = max_blocks;
     hipLaunchKernelGGL(hrr::order_keys_kernel, dim3(blocks), dim3(256), 0, stream, items, vbegin, n_items, total, bits,
-                       keys, hist);
-    hipLaunchKernelGGL(hrr::exclusive_scan_kernel, dim3(1), dim3(1024), 0, stream, hist, n_buckets);
-    hipLaunchKernelGGL(hrr::order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, keys, vbegin, total, bits, hist,
-                       order);
+                       rbits, tile, tile_tz, keys, hist);
+    uint32_t* sums = hist + n_buckets;
+    hipLaunchKernelGGL(hrr::scan_chunk_sums_kernel, dim3(n_chunks), dim3(256), 0, stream, hist, n_buckets, sums);
+    hipLaunchKernelGGL(hrr::scan_sums_kernel, dim3(1), dim3(256), 0, stream, sums, n_chunks);
+    hipLaunchKernelGGL(hrr::scan_apply_kernel, dim3(n_chunks), dim3(256), 0, stream, hist, n_buckets, sums);
+    hipLaunchKernelGGL(hrr::order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, keys, vbegin, total, key_bits,
+                       hist, order);
     return hipGetLastError();
 }

@@ -38,7 +38,7 @@ struct ItemDesc {
     uint32_t* slack_pairs;        // positions >= capacity land here (library memory)
     float* slack_weights;
     const uint32_t* order;        // processing order of the virtual eyes, or null (index order)
-    unsigned long long* counters; // CNT_PAIRS, CNT_CHUNKS, CNT_PARTIALS (device)
+    unsigned long long* counters; // CNT_PAIRS, CNT_CHUNKS, CNT_PARTIALS, CNT_PACKED (device)
     unsigned long long* partials; // (chunk, fill) of partly filled chunks
     unsigned long long capacity;  // pairs the slice can hold
     unsigned long long slack;     // pairs the slack area can hold
@@ -55,15 +55,18 @@ struct ItemDesc {
 
 // Eye-ordering description of one item: eyes are bucketed by the Morton
 // cell of their position inside the item's light box (cell = (x - lo) * scale,
-// clamped), so that consecutive tasks walk nearby parts of the hierarchy.
+// clamped), then by the low significant bits of their tile value (bit
+// reversed), so that consecutive tasks walk nearby parts of the hierarchy and
+// eyes whose shifts agree modulo a power of two (which therefore see the same
+// minima on all but the smallest index blocks) run together.
 struct OrderItem {
     const float* eyes;
     float lo[3], scale[3];
-    uint32_t n_samples, pad;
+    uint32_t n_samples, width, pixel_base, pad;
 };
 
 // Per-item device counters, one 128-byte line per item.
-enum CounterIdx { CNT_PAIRS = 0, CNT_CHUNKS = 1, CNT_PARTIALS = 2, CNT_STRIDE = 16 };
+enum CounterIdx { CNT_PAIRS = 0, CNT_CHUNKS = 1, CNT_PARTIALS = 2, CNT_PACKED = 3, CNT_STRIDE = 16 };
 
 // Kernel arguments of the persistent traversal launch.
 struct TravArgs {

@@ -356,9 +356,10 @@ int main(int argc, char** argv) {
         if (x.fill >= C) { x.fill -= C; x.chunk = next; if (x.fill == 0) x.chunk = -1; }
     }
     const unsigned long long target = std::min(count, cap);
-    std::vector<unsigned long long> fill, seg;
+    hrr::CompactScratch scratch;
+    std::vector<unsigned long long> seg;
     const unsigned long long unfilled = hrr::plan_compaction(target, K, shift, cap, slack, partials.data(),
-                                                             partials.size() / 2, 0, 0, fill, seg);
+                                                             partials.size() / 2, 0, 0, scratch, seg);
     // moves read sources that are never destinations, so order does not matter
     for (size_t s = 0; s < seg.size(); s += 3) {
         const unsigned long long src = seg[s], dst = seg[s + 1], len = seg[s + 2];
