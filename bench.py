@@ -25,8 +25,11 @@ if ROOT not in sys.path:
 
 # MI355X published peaks
 HBM_PEAK_GBS = 8000.0
-# non-packed 32-bit VALU issue: 256 CU x 64 lanes x 2.4 GHz
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# 32-bit VALU lane-operations: 256 CU x 4 SIMD x 32 lanes x 2.4 GHz = 78.6 T/s,
+# the rate behind the published fp32 vector peak (157.3 TFLOP/s = 78.6 T FMA/s).
+# The traversal's counters show the SIMDs issuing 0.33 wave64 instructions per
+# cycle, which a 16-lane (4-cycle) issue could not reach.
+VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 
 # Algorithmic 32-bit VALU lane-operations per unit of traversal work, counted
 # from the arithmetic each unit needs as gfx950 executes it (the breakdown
