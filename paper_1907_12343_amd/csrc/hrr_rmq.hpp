@@ -96,6 +96,23 @@ HRR_HD uint32_t refine(uint32_t x, int keep, uint32_t a, uint32_t b) {
     return x;
 }
 
+// The same walk for a class that meets [a,b), started from seed_candidate:
+// the seed is either the smallest member at or above a (then below b), or
+// one class step below it with bit `keep` set, so the first step lands on
+// that member.  Every step therefore ends at or above a, and only the bound
+// b is tested; the bits above j are 0u - (2u << j) (none for j = 31).
+HRR_HD uint32_t refine_inside(uint32_t x, int keep, uint32_t b) {
+    uint32_t todo = x & ~low_mask(keep);
+    while (todo) {
+        const int j = bottom_bit(todo);
+        const uint32_t step = 1u << j;
+        if (step >= b - x) break;
+        x += step;
+        todo = x & (0u - (2u << j));
+    }
+    return x;
+}
+
 // Candidate with a given low prefix: a's bits above bit `i`, a 1 at bit i,
 // and `low` (bits below i).  When that falls below a, one more bit above i is
 // set to lift it into the range before refining.  Section 2: keep a's set
@@ -268,7 +285,9 @@ HRR_HD uint32_t rmq_paper_select(uint32_t a, uint32_t b, uint32_t kr) {
     uint32_t k = most_trailing_zeros(a, b - 1u);   // no class: Algorithm 1's answer
     if (!first && !above && !at_g && z != 0u) {
         const int i = top_bit(z);
-        k = refine(seed_candidate(a, i, kr & low_mask(i)), i + 1, a, b);
+        // below g the class step 2^(i+1) is at most the range length, so its
+        // smallest member at or above a lies inside [a,b)
+        k = refine_inside(seed_candidate(a, i, kr & low_mask(i)), i + 1, b);
     }
     k = at_g ? a + t_g : k;
     k = above ? a + dlow : k;
