@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <thread>
 #include <utility>
 #include <vector>
 
@@ -88,6 +89,71 @@ inline unsigned long long plan_compaction(unsigned long long target, unsigned lo
         if (dpos == data[di].second && ++di < data.size()) dpos = data[di].first;
     }
     return unfilled;
+}
+
+// One item of a launch, as the host reads it back: its true pair count, the
+// chunks handed out, its partial-chunk list (n_partials entries from
+// partial_at in the packed list; only items that stored pairs have one) and
+// its output layout.
+struct ItemPlan {
+    unsigned long long count, chunks, n_partials, partial_at;
+    unsigned long long capacity, slack, out_offset, slack_off;
+    uint32_t shift;
+};
+
+// Plans the moves of every item of a launch: appends their segments to
+// `segments` in item order and sets stored[k] = min(count, capacity) minus the
+// positions left unfilled.  With eight or more items and 8192 or more partial
+// entries the items are cut into up to max_threads contiguous ranges of about
+// equal partial counts, planned on host threads with scratch of their own and
+// joined in item order, so the result equals the one-thread plan.  Returns
+// true when some item left positions unfilled.
+inline bool plan_items(const ItemPlan* items, size_t n, const unsigned long long* partials, unsigned max_threads,
+                       CompactScratch& scratch, std::vector<unsigned long long>& segments,
+                       unsigned long long* stored) {
+    auto plan_range = [&](size_t k0, size_t k1, CompactScratch& sc, std::vector<unsigned long long>& seg) {
+        bool lost = false;
+        for (size_t k = k0; k < k1; ++k) {
+            const ItemPlan& it = items[k];
+            const unsigned long long target = std::min(it.count, it.capacity);
+            stored[k] = 0;
+            if (target == 0) continue;
+            const unsigned long long unfilled =
+                plan_compaction(target, it.chunks, it.shift, it.capacity, it.slack, partials + 2 * it.partial_at,
+                                it.n_partials, it.out_offset, it.slack_off, sc, seg);
+            stored[k] = target - unfilled;
+            if (unfilled) lost = true;
+        }
+        return lost;
+    };
+    unsigned long long total = 0;
+    for (size_t k = 0; k < n; ++k)
+        if (std::min(items[k].count, items[k].capacity)) total += items[k].n_partials;
+    const size_t n_threads =
+        (n >= 8 && total >= 8192) ? std::min<size_t>(std::max(1u, max_threads), std::min<size_t>(8, n)) : 1;
+    if (n_threads <= 1) return plan_range(0, n, scratch, segments);
+    std::vector<size_t> cut(n_threads + 1, n);
+    cut[0] = 0;
+    size_t t = 1;
+    unsigned long long acc = 0;
+    for (size_t k = 0; k < n && t < n_threads; ++k) {
+        if (std::min(items[k].count, items[k].capacity)) acc += items[k].n_partials;
+        if (acc * n_threads >= total * t) cut[t++] = k + 1;
+    }
+    std::vector<CompactScratch> sc(n_threads - 1);
+    std::vector<std::vector<unsigned long long>> seg(n_threads - 1);
+    std::vector<char> lost(n_threads, 0);
+    std::vector<std::thread> pool;
+    for (size_t q = 1; q < n_threads; ++q)
+        pool.emplace_back([&, q] { lost[q] = plan_range(cut[q], cut[q + 1], sc[q - 1], seg[q - 1]); });
+    lost[0] = plan_range(cut[0], cut[1], scratch, segments);
+    for (auto& th : pool) th.join();
+    bool any = lost[0] != 0;
+    for (size_t q = 1; q < n_threads; ++q) {
+        any = any || lost[q];
+        segments.insert(segments.end(), seg[q - 1].begin(), seg[q - 1].end());
+    }
+    return any;
 }
 
 }  // namespace hrr

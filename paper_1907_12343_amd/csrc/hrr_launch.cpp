@@ -432,55 +432,26 @@ hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weig
             return hip_fail(e, "read partial chunks");
         if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "read partial chunks");
     }
-    // Plan every item's moves; launches with many partial chunks (many items,
-    // each touched by most waves) are planned on several host threads, each
-    // with its own scratch, over item ranges of about equal partial counts.
-    auto plan_range = [&](size_t k0, size_t k1, CompactScratch& scratch, std::vector<unsigned long long>& seg) {
-        bool lost = false;
-        for (size_t k = k0; k < k1; ++k) {
-            const unsigned long long cnt = rd[k * CNT_STRIDE + CNT_PAIRS];
-            const unsigned long long K = rd[k * CNT_STRIDE + CNT_CHUNKS];
-            const unsigned long long P =
-                std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], M[k].partial_cap);
-            S.counts[k] = cnt;
-            const ItemMeta& m = M[k];
-            const unsigned long long target = std::min(cnt, m.capacity);
-            if (target == 0) continue;
-            const unsigned long long unfilled =
-                plan_compaction(target, K, m.chunk_shift, m.capacity, m.slack, S.h_partials + 2 * part_at[k], P,
-                                m.out_offset, m.slack_off, scratch, seg);
-            S.stored[k] = target - unfilled;
-            if (unfilled) lost = true;   // pairs lost: never expected
-        }
-        return lost;
-    };
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    const size_t n_threads = (n >= 8 && total >= 8192) ? std::min<size_t>({8, (size_t)hw, n}) : 1;
-    if (n_threads <= 1) {
-        if (plan_range(0, n, S.compact, S.h_segments)) S.error |= ERR_UNFILLED;
-    } else {
-        std::vector<size_t> cut(n_threads + 1, n);
-        cut[0] = 0;
-        size_t t = 1, acc = 0;
-        for (size_t k = 0; k < n && t < n_threads; ++k) {
-            const unsigned long long cnt = rd[k * CNT_STRIDE + CNT_PAIRS];
-            if (std::min(cnt, M[k].capacity))
-                acc += (size_t)std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], M[k].partial_cap);
-            if (acc * n_threads >= total * t) cut[t++] = k + 1;
-        }
-        std::vector<CompactScratch> scratch(n_threads);
-        std::vector<std::vector<unsigned long long>> seg(n_threads);
-        std::vector<char> lost(n_threads, 0);
-        std::vector<std::thread> pool;
-        for (size_t q = 1; q < n_threads; ++q)
-            pool.emplace_back([&, q] { lost[q] = plan_range(cut[q], cut[q + 1], scratch[q], seg[q]); });
-        lost[0] = plan_range(cut[0], cut[1], S.compact, S.h_segments);
-        for (auto& th : pool) th.join();
-        for (size_t q = 0; q < n_threads; ++q) {
-            if (lost[q]) S.error |= ERR_UNFILLED;
-            if (q) S.h_segments.insert(S.h_segments.end(), seg[q].begin(), seg[q].end());
-        }
+    // Plan every item's moves (on several host threads for launches with many
+    // partial chunks: many items, each touched by most waves).
+    std::vector<ItemPlan> plan(n);
+    for (size_t k = 0; k < n; ++k) {
+        const ItemMeta& m = M[k];
+        ItemPlan& p = plan[k];
+        p.count = rd[k * CNT_STRIDE + CNT_PAIRS];
+        p.chunks = rd[k * CNT_STRIDE + CNT_CHUNKS];
+        p.n_partials = std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], m.partial_cap);
+        p.partial_at = part_at[k];
+        p.capacity = m.capacity;
+        p.slack = m.slack;
+        p.out_offset = m.out_offset;
+        p.slack_off = m.slack_off;
+        p.shift = m.chunk_shift;
+        S.counts[k] = p.count;
     }
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    if (plan_items(plan.data(), n, S.h_partials, std::min(8u, hw), S.compact, S.h_segments, S.stored.data()))
+        S.error |= ERR_UNFILLED;   // pairs lost: never expected
     const size_t n_seg = S.h_segments.size() / 3;
     if (n_seg) {
         if ((e = S.segments.ensure(S.h_segments.size() * sizeof(unsigned long long))) != hipSuccess)

@@ -379,6 +379,76 @@ int main(int argc, char** argv) {
 """
 
 
+PLAN_ITEMS_HARNESS = r"""
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+#include "hrr_compact.hpp"
+// Random launches of many items (random partial-chunk lists, capacities below,
+// equal to and above the counts, empty items); plan_items on 1 and on 8
+// threads must give the same segments, stored counts and unfilled flag.
+// args: items partials_per_item seed
+int main(int argc, char** argv) {
+    const size_t n = strtoull(argv[1], 0, 10);
+    const unsigned long long per = strtoull(argv[2], 0, 10);
+    std::mt19937_64 rng(strtoull(argv[3], 0, 10));
+    std::vector<hrr::ItemPlan> items(n);
+    std::vector<unsigned long long> partials;
+    unsigned long long off = 0;
+    for (size_t k = 0; k < n; ++k) {
+        hrr::ItemPlan& it = items[k];
+        it.shift = 7 + (unsigned)(rng() % 7);
+        const unsigned long long C = 1ull << it.shift;
+        const unsigned long long P = rng() % (2 * per + 1);
+        it.count = (k % 9 == 4) ? 0 : P * C / 2 + rng() % (64 * C);
+        const int mode = (int)(rng() % 3);
+        it.capacity = mode == 0 ? it.count : mode == 1 ? it.count / 2 : it.count + rng() % 1000;
+        it.chunks = it.count / C + P + 1;
+        it.slack = 2 * P * C;
+        it.n_partials = it.count ? P : 0;
+        it.partial_at = partials.size() / 2;
+        it.out_offset = off;
+        it.slack_off = off;
+        off += it.capacity + it.slack;
+        for (unsigned long long q = 0; q < it.n_partials; ++q) {
+            partials.push_back(rng() % it.chunks);
+            partials.push_back(rng() % C);
+        }
+    }
+    std::vector<unsigned long long> s1, s8, st1(n), st8(n);
+    hrr::CompactScratch c1, c8;
+    const bool l1 = hrr::plan_items(items.data(), n, partials.data(), 1, c1, s1, st1.data());
+    const bool l8 = hrr::plan_items(items.data(), n, partials.data(), 8, c8, s8, st8.data());
+    if (l1 != l8 || s1 != s8 || st1 != st8) { printf("mismatch\n"); return 1; }
+    printf("ok segments=%zu partials=%zu\n", s1.size() / 3, partials.size() / 2);
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def plan_items_harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("plan_items")
+    src = d / "plan_items.cpp"
+    src.write_text(PLAN_ITEMS_HARNESS)
+    exe = d / "plan_items"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-pthread", "-I", CSRC, str(src), "-o", str(exe)],
+                   check=True)
+    return str(exe)
+
+
+@pytest.mark.parametrize("items,per,seed", [(3, 100, 1), (8, 2000, 2), (40, 400, 3), (256, 900, 4),
+                                            (1000, 20, 5)])
+def test_threaded_compaction_plan_equals_one_thread(plan_items_harness, items, per, seed):
+    """Many-item launches plan their hole filling on host threads over item
+    ranges; the joined plan must equal the one-thread plan exactly."""
+    out = subprocess.run([plan_items_harness, str(items), str(per), str(seed)], capture_output=True,
+                         text=True)
+    assert out.returncode == 0, out.stdout + out.stderr
+    assert out.stdout.startswith("ok")
+
+
 @pytest.fixture(scope="module")
 def compact_harness(tmp_path_factory):
     d = tmp_path_factory.mktemp("compact")

@@ -153,6 +153,36 @@ def test_shift_offset_and_pixel_base(ctx, orc, tiny, tiny_oracle):
     h.free()
 
 
+@pytest.mark.parametrize("kind", ["zero", "random", "odd"])
+def test_any_tile_values(orc, tiny, tiny_oracle, kind):
+    """The eye order groups eyes by the low significant bits of their tile
+    value; tiles without the permutation-times-2^20 structure (all zero: no
+    class bits; full 32-bit values; odd values) must give the same set as
+    the oracle."""
+    import paper_1907_12343_amd as hrr
+    rng = np.random.default_rng(7)
+    if kind == "zero":
+        tile = np.zeros(4096, np.uint32)
+    elif kind == "random":
+        tile = rng.integers(0, 2**32, 4096, dtype=np.uint64).astype(np.uint32)
+    else:
+        tile = (2 * rng.integers(0, 2**20, 4096) + 1).astype(np.uint32)
+    c = hrr.Context(tile)
+    try:
+        h = c.build_hierarchy(tiny["lights"], leaf_size=1)
+        sel = np.arange(tiny["eyes"].shape[0])
+        exp = pair_keys_from_oracle(
+            orc.accept_eyes(tiny["eyes"], sel, tiny["width"], 0, tile, tiny_oracle["lights_sorted"],
+                            tiny["s"], lists=True), sel)
+        for reorder in (True, False):
+            pairs, n, _ = c.traverse_all(h, _eyes_t(c, tiny["eyes"]), tiny["s"], tiny["width"],
+                                         reorder=reorder)
+            assert np.array_equal(pair_keys_from_gpu(pairs), exp)
+        h.free()
+    finally:
+        c.close()
+
+
 def test_overflow_reports_true_count(ctx, tiny, tiny_oracle):
     import paper_1907_12343_amd as hrr
     import torch
