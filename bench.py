@@ -62,6 +62,12 @@ def frame_workload(args):
     import synth
 
     fr = synth.frame()
+    ns = max(1, args.samples)
+    if ns > 1:
+        # several samples per eye (Section 3): the first 1080 / N pixel rows,
+        # so that eyes x samples stays at about one frame of virtual eyes
+        rows = max(1, 1080 // ns)
+        fr = dict(fr, eyes=np.ascontiguousarray(fr["eyes"][:rows * fr["width"]]))
     ctx = hrr.Context(fr["tile"], device=0)
     t0 = time.time()
     h = ctx.build_hierarchy(fr["lights"], leaf_size=fr["leaf"])
@@ -75,13 +81,17 @@ def frame_workload(args):
     build_dev_s = time.perf_counter() - t0
     hd.free()
     eyes = torch.from_numpy(fr["eyes"]).to("cuda:0")
-    n_eyes = fr["eyes"].shape[0]
+    n_eyes = fr["eyes"].shape[0] * ns           # virtual eyes (eye x sample)
     method = RMQ_METHODS[args.rmq]
     kw = dict(rmq_method=method, eyes_per_wave=args.epw, stack_entries=args.stack)
+    if ns > 1:
+        kw.update(n_samples=ns, psi_s0=PSI_S0)
     n = ctx.count(h, eyes, fr["s"], fr["width"], **kw)
     pairs = torch.empty((max(n, 1), 2), dtype=torch.int32, device="cuda:0")
+    weights = torch.empty((max(n, 1),), dtype=torch.float32, device="cuda:0") if args.weights else None
+    kw["weights"] = weights
     # one untimed launch with counters on: units of work for the roofline
-    _, _, st = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, stats=True, **kw)
+    st = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, stats=True, **kw)[2]
     for _ in range(args.warmup):
         ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, **kw)
     stream = torch.cuda.current_stream()
@@ -94,7 +104,7 @@ def frame_workload(args):
     for _ in range(args.steps):
         # timing=True: the library brackets the traversal kernel with HIP
         # events on this same stream
-        _, got, stt = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, timing=True, **kw)
+        _, got, stt = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, timing=True, **kw)[:3]
         assert got == n
         kernel_ms.append(stt["kernel_ms"])
     e1.record(stream)
@@ -119,8 +129,7 @@ def frame_workload(args):
         "vs_baseline": None,
         "dtype": "u32+f32",
         "data": "synthetic",
-        "config": {"workload": "frame: 1920x1080 eyes x 2^20 lights, 64-Gaussian mixture "
-                               "sigma 0.02, s=1e-4, leaf 1, one launch",
+        "config": {"workload": _frame_name(ns, args.weights),
                    "n_eyes": n_eyes, "n_lights": int(fr["lights"].shape[0]),
                    "rmq": args.rmq, "parallelism": "1 GPU"},
         "pairs_per_s": n / (ms * 1e-3),
@@ -134,16 +143,20 @@ def frame_workload(args):
         "algorithmic_lane_ops": ops,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": _traffic_bytes(args)},
+                     "traffic": _traffic_bytes(args) if (ns == 1 and not args.weights) else None},
     }
+    if ns > 1:
+        line["config"]["samples_per_eye"] = ns
+        line["config"]["psi_s0"] = PSI_S0
     traffic = line["roofline"]["traffic"]
     if traffic is not None:
-        # everything that leaves the L2s (Infinity Cache hits included): the
-        # walk is bound by this miss stream, not by VALU issue
+        # everything that leaves the L2s (Infinity Cache hits included),
+        # beside the ALU roofline: the walk is co-limited by VALU issue and
+        # the vector-memory address path, not by this stream
         line["memory_side"] = {"bytes": traffic, "TB_per_s": traffic / (gpu_ms * 1e-3) / 1e12,
                                "frac_of_hbm_peak": traffic / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline_frame(fr, n_eyes, args)
+        line["cpu_baseline"] = cpu_baseline_frame(fr, fr["eyes"].shape[0], args, ns)
     h.free()
     ctx.close()
     return line
@@ -182,18 +195,34 @@ def _traffic_bytes(args, path=TRAFFIC_FILE):
     return (rec["fetch_kib_scaled"] + rec["write_kib_scaled"]) * 1024.0
 
 
-def cpu_baseline_frame(fr, n_eyes, args):
+def _frame_name(ns, weights):
+    name = "frame: 1920x1080 eyes x 2^20 lights, 64-Gaussian mixture sigma 0.02, s=1e-4, leaf 1"
+    if ns > 1:
+        name = ("frame rows 0..%d (1920x%d eyes) x %d samples per eye x 2^20 lights, "
+                "64-Gaussian mixture sigma 0.02, s=1e-4, leaf 1" % (1080 // ns - 1, 1080 // ns, ns))
+    if weights:
+        name += ", 1/p weights"
+    return name + ", one launch"
+
+
+# Section 3's extra rotation of sample n: psi(n) = s0 + n alpha (mod 1), s0 fixed here
+PSI_S0 = 0x6A09E667
+
+
+def cpu_baseline_frame(fr, n_eyes, args, ns=1):
     import numpy as np
     import oracle
     threads = max(1, min(16, os.cpu_count() or 1))
     ls = fr["lights"][oracle.morton_order(fr["lights"])]   # the oracle's own light order
-    sel = np.linspace(0, n_eyes - 1, args.cpu_eyes).astype(np.uint32)
+    sel = np.linspace(0, n_eyes - 1, max(1, args.cpu_eyes // ns)).astype(np.uint32)
     t0 = time.perf_counter()
-    oracle.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], ls, fr["s"], threads=threads)
+    oracle.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], ls, fr["s"], n_samples=ns,
+                       psi_s0=PSI_S0 if ns > 1 else 0, threads=threads)
     dt = time.perf_counter() - t0
-    return {"value": sel.size / dt, "unit": "eyes/s", "cores": threads, "kind": "oracle",
-            "sample": "%d eyes evenly spaced over the frame, all-pairs test against all %d "
-                      "lights (%.1f s)" % (sel.size, ls.shape[0], dt)}
+    return {"value": sel.size * ns / dt, "unit": "eyes/s", "cores": threads, "kind": "oracle",
+            "sample": "%d eyes%s evenly spaced over the frame, all-pairs test against all %d "
+                      "lights (%.1f s)" % (sel.size, " x %d samples" % ns if ns > 1 else "",
+                                           ls.shape[0], dt)}
 
 
 def rangemin_workload(args):
@@ -498,6 +527,9 @@ def main():
     p.add_argument("--rmq", default="paper", choices=list(RMQ_METHODS),
                    help="range-minimum method: paper (bit-parallel flip-position selection, "
                         "default), direct, paper_full (sweeps as loops), paper_loop (pruned loops)")
+    p.add_argument("--samples", type=int, default=1,
+                   help="frame: samples per eye (rotation psi(n) per sample; fewer pixel rows)")
+    p.add_argument("--weights", action="store_true", help="frame: also write 1/p per pair")
     p.add_argument("--epw", type=int, default=1)
     p.add_argument("--stack", type=int, default=512)
     p.add_argument("--traffic-kib", type=float, nargs=2, default=None,
