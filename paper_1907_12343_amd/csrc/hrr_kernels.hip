@@ -534,16 +534,21 @@ void traverse_kernel(TravArgs A) {
     uint32_t q = blockIdx.x % kQueues;
     uint32_t queues_left = kQueues;
     for (;;) {
-        const uint32_t q_lo = A.queue_begin[q];
-        const uint32_t q_hi = A.queue_begin[q + 1];
-        uint32_t t = 0;
-        if (lane == 0) t = atomicAdd(A.queues + q * kQueueStride, 1u);
-        t = q_lo + uni(t);
-        if (t >= q_hi) {
+        uint32_t i = 0;
+        if (lane == 0) i = atomicAdd(A.queues + q * kQueueStride, 1u);
+        i = uni(i);
+        // the i-th task of queue q; increasing in i, so the first one past the
+        // end means the queue is exhausted
+        const uint32_t sh = A.interleave_shift;
+        const uint64_t t64 = sh ? (((((uint64_t)(i >> sh)) * kQueues + q) << sh) | (i & ((1u << sh) - 1u)))
+                                : (uint64_t)A.queue_begin[q] + i;
+        const uint64_t end = sh ? (uint64_t)A.n_tasks : (uint64_t)A.queue_begin[q + 1];
+        if (t64 >= end) {
             if (--queues_left == 0) break;
             q = (q + 1) % kQueues;
             continue;
         }
+        const uint32_t t = (uint32_t)t64;
 
         // item of task t: largest k with task_begin[k] <= t
         uint32_t lo = 0, hi = A.n_items;

@@ -103,15 +103,23 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     std::vector<ItemMeta>& M = S.meta;
     M.assign(n, ItemMeta{});
     unsigned long long slack_total = 0, partial_total = 0;
-    // A wave walks the queues in the cyclic order q0, q0+1, ..., q0-1 and the
-    // tasks of each queue in increasing order, so the items it meets are
-    // nondecreasing except at the one wrap from the last queue to the first:
-    // it leaves an item (and publishes a partly filled chunk) at most twice,
-    // and at most once in a one-item launch.  Every allocated chunk other
-    // than those is full, so the pairs stored past the capacity (slack) and
-    // the holes below it are bounded by partial_cap chunks each; a slack of
-    // twice that lets the compaction fill every hole below min(count, capacity).
-    const uint64_t leaves_per_wave = n > 1 ? 2 : 1;
+    // Queue layout.  Launches of several items with 2^19 or more tasks use
+    // interleaved chunks of 2^13 tasks (queue q owns chunks q, q + 8, ...):
+    // all XCDs then work on the same heavy items at a time and the Infinity
+    // Cache holds fewer hierarchies at once (256 caches: kernel 70.3 -> 66.5
+    // ms); other launches use eight contiguous slices of equal cost.
+    const uint32_t il_shift = (n > 1 && tasks >= (1ull << 19)) ? 13u : 0u;
+    // A wave visits each queue once (cyclic order from its own) and takes a
+    // queue's tasks in increasing order, so within one queue visit the items
+    // it meets are nondecreasing and it leaves an item (publishing a partly
+    // filled chunk) at most once.  With contiguous slices the queues are in
+    // task order too: at most twice per item (the one wrap), once in a
+    // one-item launch; with interleaved chunks at most once per queue visit.
+    // Every allocated chunk other than those is full, so the pairs stored past
+    // the capacity (slack) and the holes below it are bounded by partial_cap
+    // chunks each; a slack of twice that lets the compaction fill every hole
+    // below min(count, capacity).
+    const uint64_t leaves_per_wave = il_shift ? kQueues : (n > 1 ? 2 : 1);
     for (size_t k = 0; k < n; ++k) {
         const uint64_t wk = std::max<uint64_t>(1, std::min<uint64_t>(waves, tasks_of[k]));
         const uint64_t pk = std::max<uint64_t>(1, std::min<uint64_t>(leaves_per_wave * waves, tasks_of[k]));
@@ -349,6 +357,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         A.n_items = (uint32_t)n;
         A.n_tasks = (uint32_t)tasks;
         for (uint32_t q = 0; q <= kQueues; ++q) A.queue_begin[q] = qbegin[q];
+        A.interleave_shift = il_shift;
         A.queues = static_cast<uint32_t*>(S.queues.p);
         A.tile = ctx->d_tile;
         A.spill = static_cast<unsigned long long*>(S.spill.p);

@@ -74,13 +74,13 @@ struct TravArgs {
     const uint32_t* task_begin;   // n_items + 1 prefix of tasks per item
     uint32_t n_items, n_tasks;
     uint32_t* queues;             // kQueues work-queue heads, kQueueStride words apart
-    uint32_t queue_begin[9];      // queue q owns tasks [queue_begin[q], queue_begin[q + 1])
+    uint32_t queue_begin[9];      // queue q owns tasks [queue_begin[q], queue_begin[q + 1]) ...
     const uint32_t* tile;         // 64 x 64 shifts
     unsigned long long* spill;    // per-wave spill stacks (uint2 entries)
     uint32_t spill_cap;           // entries per wave
     uint32_t stack_cap;           // LDS stack entries per wave (power of two)
     uint32_t lds_per_wave;        // bytes
-    uint32_t pad0;
+    uint32_t interleave_shift;    // ... or, if > 0, chunks q, q + 8, q + 16, ... of 2^shift tasks
     unsigned long long* stats;    // 8 counters or null
     uint32_t* error;              // set non-zero on an internal failure
 };
@@ -89,9 +89,10 @@ constexpr int kWave = 64;
 constexpr int kWavesPerBlock = 4;
 constexpr uint32_t kMaxItemsPerLaunch = 1024;
 // One work queue per XCD: queue q owns a contiguous slice of the task list
-// (TravArgs::queue_begin); blocks are dispatched to the 8 XCDs round-robin,
-// so block b starts on queue b % 8 and its L2 sees a contiguous (spatially
-// ordered) slice of the eyes.
+// (TravArgs::queue_begin), or every eighth chunk of 2^interleave_shift tasks;
+// blocks are dispatched to the 8 XCDs round-robin, so block b starts on queue
+// b % 8.  Slices give each L2 a contiguous (spatially ordered) part of the
+// eyes; interleaved chunks keep all XCDs on the same items at a time.
 constexpr uint32_t kQueues = 8;
 constexpr uint32_t kQueueStride = 32;   // 128 bytes between queue heads
 static_assert(sizeof(TravArgs::queue_begin) == (kQueues + 1) * sizeof(uint32_t), "one slice per queue");

@@ -136,6 +136,51 @@ def test_batched_with_empty_items(ctx):
     h0.free()
 
 
+def test_batched_interleaved_queues_equal_plain_and_oracle(ctx, orc, hrr):
+    """A launch of several items with 2^19 or more tasks hands the XCD queues
+    interleaved chunks of tasks (and lets a wave leave an item up to eight
+    times); every item must still equal its plain launch, also when one item
+    overflows its slice."""
+    import torch
+    caches = []
+    for c in range(18):
+        d = _small_cache(c, 1 << 12, 1 << 15)
+        reps = -(-(1 << 15) // d["eyes"].shape[0])
+        d["eyes"] = np.ascontiguousarray(np.tile(d["eyes"], (reps, 1))[:1 << 15])
+        caches.append(d)
+    assert sum(d["eyes"].shape[0] for d in caches) >= 1 << 19
+    hs = [ctx.build_hierarchy(d["lights"]) for d in caches]
+    eyes = [_dev(ctx, d["eyes"]) for d in caches]
+    counts = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
+    caps = list(counts)
+    caps[5] = counts[5] // 2       # overflows
+    caps[9] = counts[9] + 777      # room to spare
+    offs = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
+    pairs = torch.full((int(offs[-1]), 2), -1, dtype=torch.int32, device=ctx.torch_device)
+    items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=int(offs[k]),
+                  out_capacity=int(caps[k]))
+             for k, (h, e, d) in enumerate(zip(hs, eyes, caches))]
+    with pytest.raises(hrr.OverflowResult) as ei:
+        ctx.traverse_batched(items, pairs)
+    assert [int(x) for x in ei.value.counts] == counts
+    rng = np.random.default_rng(11)
+    for k, d in enumerate(caches):
+        sl = pairs[offs[k]:offs[k] + min(caps[k], counts[k])]
+        keys = pair_keys_from_gpu(sl)
+        full = _plain_keys(ctx, hs[k], eyes[k], d["s"], d["width"])
+        if k == 5:
+            assert keys.size == caps[5] and np.unique(keys).size == keys.size
+            assert np.isin(keys, full).all()
+            continue
+        assert np.array_equal(keys, full)
+        if k % 6 == 0:
+            sel = np.sort(rng.choice(d["eyes"].shape[0], 8, replace=False)).astype(np.uint32)
+            want = _oracle_keys(orc, d["lights"], d["eyes"], sel, d["width"], 0, d["s"])
+            assert np.array_equal(select_pairs_of_eyes(sl, sel), want)
+    for h in hs:
+        h.free()
+
+
 def test_batched_256_caches_counts_match_plain(ctx):
     """The 256-cache workload at its real sizes: per-item counts of one
     counting launch equal those of 256 plain launches."""
