@@ -2,16 +2,22 @@
 // rotated base-2 radical inverse (Pantaleoni, "Blue-Noise Dithered QMC
 // Hierarchical Russian Roulette").
 //
-//   rmq_kernel       one range-minimum query per lane (Section 1, v(a,b);
-//                    Section 2, Algorithms 2-3), streaming u32 arrays.
+//   rmq_kernel       range-minimum queries (Section 1, v(a,b); Section 2,
+//                    Algorithms 2-3), eight per thread, streaming u32 arrays.
 //   traverse_kernel  persistent wavefronts that pull (item, eye group) tasks
-//                    from a device work queue and cull every eye's pairs by a
-//                    top-down walk of its item's light hierarchy (Section 1).
+//                    from eight per-XCD work queues and cull every eye's pairs
+//                    by a top-down walk of its item's light hierarchy
+//                    (Section 1).
+//   around it        the eye order (bucket keys, a multi-block scan, scatter),
+//                    the packing of the partly filled output chunks after a
+//                    traversal, and the moves that make every item's output
+//                    dense (move_pairs_kernel).
 //
 // Wavefront design.  One wave owns a group of 1..8 eyes.  Its stack of
 // pending hierarchy nodes lives in LDS and is shared by the 64 lanes: each
-// iteration pops up to 64 nodes (one per lane), each lane fetches its node's
-// 64-byte record (both children's boxes), derives the children's range minima
+// iteration pops up to 64 nodes (one per lane), each lane obtains its node's
+// 64-byte record (both children's boxes; neighbouring lanes fetch their two
+// records as shared 32-byte halves), derives the children's range minima
 // -- the child that contains the parent's argmin inherits it, the other needs
 // one range-minimum query -- bounds both children, and the survivors are
 // pushed back with ballot/mbcnt compaction.  Leaves with one light are tested
