@@ -169,11 +169,17 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1907_12343_amd", "csrc", f)
 
 
 def kernel_source_digest():
+    """SHA-256 of the kernel sources with comments and blank space removed, so
+    that only a change of the code itself invalidates recorded counters."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)   # block comments
+        text = re.sub(r"//[^\n]*", " ", text)                # line comments
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
