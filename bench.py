@@ -279,13 +279,14 @@ def rangemin_workload(args):
         import oracle
         threads = max(1, min(16, os.cpu_count() or 1))
         a2, b2, r2 = synth.rangemin_check_queries()
+        m = min(args.cpu_queries, a2.size)
         t0 = time.perf_counter()
-        oracle.rmq_scan(a2[:8192], b2[:8192], r2[:8192], threads=threads)
+        oracle.rmq_scan(a2[:m], b2[:m], r2[:m], threads=threads)
         dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {"value": 8192 / dt, "unit": "queries/s", "cores": threads,
+        line["cpu_baseline"] = {"value": m / dt, "unit": "queries/s", "cores": threads,
                                 "kind": "oracle",
-                                "sample": "8192 queries with b-a <= 2^16 by scanning (%.1f s)"
-                                          % dt}
+                                "sample": "%d queries with b-a <= 2^16 by scanning (%.1f s)"
+                                          % (m, dt)}
     ctx.close()
     return line
 
@@ -542,7 +543,10 @@ def main():
                    metavar=("FETCH", "WRITE"),
                    help="FETCH_SIZE and WRITE_SIZE (KiB per launch) of the traversal kernel "
                         "from rocprofv3 --pmc runs, already scaled by the copy-kernel factors")
-    p.add_argument("--cpu-eyes", type=int, default=256)
+    p.add_argument("--cpu-eyes", type=int, default=3072,
+                   help="frame: eyes in the oracle's timed sample (about 10 s on 16 threads)")
+    p.add_argument("--cpu-queries", type=int, default=65536,
+                   help="rangemin: queries in the oracle's timed sample (about 6 s on 16 threads)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     args = p.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
