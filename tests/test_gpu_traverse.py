@@ -313,6 +313,46 @@ def test_invalid_arguments(ctx, tiny):
     h.free()
 
 
+def _bitrev32(x):
+    """Bit reversal of u32 values held in an int64 tensor (Section 2's radical
+    inverse in 32-bit fixed point), by the usual swap of halves, bytes, ..."""
+    x = ((x >> 1) & 0x55555555) | ((x & 0x55555555) << 1)
+    x = ((x >> 2) & 0x33333333) | ((x & 0x33333333) << 2)
+    x = ((x >> 4) & 0x0F0F0F0F) | ((x & 0x0F0F0F0F) << 4)
+    x = ((x >> 8) & 0x00FF00FF) | ((x & 0x00FF00FF) << 8)
+    return ((x >> 16) & 0xFFFF) | ((x & 0xFFFF) << 16)
+
+
+def _assert_every_pair_passes_its_test(pairs, fr, perm, chunk=1 << 27):
+    """Soundness over the whole launch: every emitted (j, i) has valid indices
+    and xi_ij < ceil(min(1, s / d^2) 2^32), with d^2 = (dx dx + dy dy) + dz dz
+    in separately rounded binary32 operations (plain torch ops, one per
+    kernel) and xi_ij = bitreverse(i) + r_j mod 2^32."""
+    import torch
+    dev = pairs.device
+    eyes = torch.from_numpy(fr["eyes"]).to(dev)
+    lights = torch.from_numpy(np.ascontiguousarray(fr["lights"][perm])).to(dev)
+    tile = torch.from_numpy(fr["tile"].astype(np.int64)).to(dev)
+    W = fr["width"]
+    s = torch.tensor(fr["s"], dtype=torch.float32, device=dev)
+    two32 = float(2 ** 32)
+    for at in range(0, pairs.shape[0], chunk):
+        pc = pairs[at:at + chunk].to(torch.int64) & 0xFFFFFFFF
+        j, i = pc[:, 0], pc[:, 1]
+        assert int(j.max()) < eyes.shape[0] and int(i.max()) < lights.shape[0]
+        e = eyes[j]
+        lt = lights[i]
+        dx = lt[:, 0] - e[:, 0]
+        dy = lt[:, 1] - e[:, 1]
+        dz = lt[:, 2] - e[:, 2]
+        d2 = (dx * dx + dy * dy) + dz * dz
+        p = torch.clamp(s / d2, max=1.0)
+        r = tile[(j % W & 63) * 64 + (j // W & 63)]
+        xi = (_bitrev32(i) + r) & 0xFFFFFFFF
+        assert bool((xi.to(torch.float64) < torch.ceil(p.to(torch.float64) * two32)).all())
+        del pc, j, i, e, lt, dx, dy, dz, d2, p, r, xi
+
+
 def test_frame_scale_sampled(ctx, orc):
     """1920x1080 eyes against 2^20 Gaussian-mixture lights in one launch (the
     benchmark shape); sampled eyes compared pair for pair with the oracle, and
@@ -334,6 +374,7 @@ def test_frame_scale_sampled(ctx, orc):
     c0 = per_eye_counts(pairs, n_eyes)
     assert int(c0.sum()) == n
     assert np.array_equal(c0[sel], out["count"].astype(np.int64))
+    _assert_every_pair_passes_its_test(pairs, fr, perm)
     del pairs
     torch.cuda.empty_cache()
     p2, n2, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n, rmq_method=1)
