@@ -82,10 +82,9 @@ void release_scratch(LaunchScratch& S) {
     S.misc.release();
     S.spill.release();
     S.partials.release();
-    S.packed.release();
+    S.plan.release();
     S.slack_pairs.release();
     S.slack_weights.release();
-    S.segments.release();
     S.order_keys.release();
     S.order_idx.release();
     S.order_hist.release();
@@ -95,9 +94,6 @@ void release_scratch(LaunchScratch& S) {
     if (S.h_pinned) (void)hipHostFree(S.h_pinned);
     S.h_pinned = nullptr;
     S.h_pinned_n = 0;
-    if (S.h_partials) (void)hipHostFree(S.h_partials);
-    S.h_partials = nullptr;
-    S.h_partials_n = 0;
     if (S.ev_begin) (void)hipEventDestroy(S.ev_begin);
     if (S.ev_end) (void)hipEventDestroy(S.ev_end);
     S.ev_begin = S.ev_end = nullptr;
@@ -381,7 +377,7 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
         launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, reorder, pairs, weights, stream, timing);
     if (st != HRR_OK) return st;
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "traverse");
-    if ((st = finish_items(ctx, S, pairs, weights, stream)) != HRR_OK) return st;
+    if ((st = finish_items(ctx, S)) != HRR_OK) return st;
     const size_t n = items.size();
     bool overflow = false;
     uint64_t total = 0;

@@ -1,159 +1,99 @@
-// hrr_compact.hpp -- host planning of the output compaction that follows a
-// traversal launch (no device calls; unit-tested on the CPU).
+// hrr_compact.hpp -- per-item arithmetic of the output compaction that follows
+// a traversal launch; used by the device kernels (compact_plan_kernel,
+// compact_move_kernel) and by the CPU tests, which emulate those kernels with
+// these same functions.
 //
-// The kernel hands out output chunks of C = 2^shift pairs, one atomic per
+// The traversal hands out output chunks of C = 2^shift pairs, one atomic per
 // chunk; a wave that leaves an item publishes its last, partly filled chunk
 // as (chunk, fill).  Positions below the caller's capacity are in the
 // caller's slice, positions in [capacity, capacity + slack) in a library
 // slack area, later ones are dropped (the count stays exact).  To make the
-// first target = min(count, capacity) positions dense, the pairs stored at
-// or past `target` are moved into the holes below it (the unfilled tails of
-// partly filled chunks).
+// first target = min(count, capacity) positions dense, the pairs stored at or
+// past `target` are moved into the holes below it:
+//   holes -- the unfilled tails [c C + f, min((c + 1) C, target)) of the
+//            partly filled chunks, in the order of the item's partial list;
+//   data  -- the stored positions [max(c C, target), min(c C + fill_c, limit))
+//            of the chunks c = c0, c0 + 1, ... (c0 = target / C) up to the
+//            last chunk handed out below limit = capacity + slack, where
+//            fill_c = C except for partly filled chunks.
+// Moved element e (0 <= e < min(total hole length, total data length)) goes
+// from the e-th data position to the e-th hole position.  Sources lie at or
+// past target and destinations below it, so moves never overlap.
+//
+// Bounds.  Every chunk handed out is full or on the partial list (a wave
+// holds a chunk only while its fill is positive and publishes it when it
+// leaves), so with count <= capacity the chunks past c0 number at most
+// n_partials + 1; with count > capacity they end at limit, at most
+// slack / C + 2.  The launch sizes slack = 2 * partial_cap * C, so an item
+// never has more than 2 * partial_cap + 2 data chunks.
 #pragma once
 
 #include <stdint.h>
 
-#include <algorithm>
-#include <thread>
-#include <utility>
-#include <vector>
+#ifndef HRR_HD   // host and device inline functions (also defined by hrr_rmq.hpp)
+#if defined(__HIPCC__)
+#define HRR_HD __host__ __device__ __forceinline__
+#else
+#define HRR_HD inline
+#endif
+#endif
 
 namespace hrr {
 
-// Source offsets with this bit set are slack-area offsets.
-constexpr unsigned long long kSlackFlag = 1ull << 63;
-
-// Reusable scratch of plan_compaction (keeps its capacity between calls).
-struct CompactScratch {
-    std::vector<unsigned long long> fill;
-    std::vector<std::pair<unsigned long long, unsigned long long>> holes, data;
+// Per-item quantities of the compaction.
+struct CompactGeom {
+    unsigned long long target;   // min(count, capacity): positions that must end up dense
+    unsigned long long C;        // pairs per chunk
+    unsigned long long limit;    // capacity + slack: stored positions are below this
+    unsigned long long c0;       // first data chunk
+    unsigned long long nd;       // number of data chunks
+    unsigned long long P;        // entries of the partial list that count
 };
 
-// Appends (source, destination, length) triples to `segments` (sources are
-// out_offset + position, or kSlackFlag | (slack_off + position - capacity);
-// destinations out_offset + position) and returns the number of positions
-// below `target` left unfilled (0 whenever the slack holds twice the chunks
-// of all partial chunks).  partials: n_partials (chunk, fill) pairs in any
-// order; chunks: the number of chunks handed out.
-inline unsigned long long plan_compaction(unsigned long long target, unsigned long long chunks, uint32_t shift,
-                                          unsigned long long capacity, unsigned long long slack,
-                                          const unsigned long long* partials, unsigned long long n_partials,
-                                          unsigned long long out_offset, unsigned long long slack_off,
-                                          CompactScratch& scratch, std::vector<unsigned long long>& segments) {
-    if (target == 0) return 0;
-    const unsigned long long C = 1ull << shift;
-    const unsigned long long limit = capacity + slack;   // stored positions are below this
-    // Holes: tails of partly filled chunks below the target.  Data: chunks
-    // c0 = target / C .. up to the limit (at most n_partials + 1 of them when
-    // the count fits), full except the partly filled ones.  Holes and data
-    // pair up in any order, so nothing is sorted.
-    std::vector<unsigned long long>& fill = scratch.fill;
-    std::vector<std::pair<unsigned long long, unsigned long long>>& holes = scratch.holes;
-    std::vector<std::pair<unsigned long long, unsigned long long>>& data = scratch.data;
-    holes.clear();
-    data.clear();
-    const unsigned long long c0 = target / C;
-    const unsigned long long c_end = std::min<unsigned long long>(chunks, (limit + C - 1) / C);
-    fill.assign(c_end > c0 ? (size_t)(c_end - c0) : 0u, C);
-    for (unsigned long long q = 0; q < n_partials; ++q) {
-        const unsigned long long c = partials[2 * q], f = partials[2 * q + 1];
-        const unsigned long long lo = c * C + f;
-        const unsigned long long hi = std::min((c + 1) * C, target);
-        if (lo < hi) holes.push_back({lo, hi});
-        if (c >= c0 && c < c_end) fill[c - c0] = f;
-    }
-    for (unsigned long long c = c0; c < c_end; ++c) {
-        const unsigned long long lo = std::max(c * C, target);
-        const unsigned long long hi = std::min(c * C + fill[c - c0], limit);
-        // a chunk that straddles the capacity gives two segments
-        if (lo < std::min(hi, capacity)) data.push_back({lo, std::min(hi, capacity)});
-        if (std::max(lo, capacity) < hi) data.push_back({std::max(lo, capacity), hi});
-    }
-    unsigned long long unfilled = 0;
-    size_t hi_ = 0, di = 0;
-    unsigned long long hpos = holes.empty() ? 0 : holes[0].first;
-    unsigned long long dpos = data.empty() ? 0 : data[0].first;
-    while (hi_ < holes.size()) {
-        if (di >= data.size()) {
-            unfilled += holes[hi_].second - hpos;
-            if (++hi_ < holes.size()) hpos = holes[hi_].first;
-            continue;
-        }
-        const unsigned long long len = std::min(holes[hi_].second - hpos, data[di].second - dpos);
-        segments.push_back(dpos < capacity ? out_offset + dpos : (kSlackFlag | (slack_off + dpos - capacity)));
-        segments.push_back(out_offset + hpos);
-        segments.push_back(len);
-        hpos += len;
-        dpos += len;
-        if (hpos == holes[hi_].second && ++hi_ < holes.size()) hpos = holes[hi_].first;
-        if (dpos == data[di].second && ++di < data.size()) dpos = data[di].first;
-    }
-    return unfilled;
+HRR_HD unsigned long long umin64(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
+HRR_HD unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+
+HRR_HD CompactGeom compact_geom(unsigned long long count, unsigned long long chunks, unsigned long long listed,
+                                unsigned long long partial_cap, unsigned long long capacity,
+                                unsigned long long slack, uint32_t shift) {
+    CompactGeom g;
+    g.target = umin64(count, capacity);
+    g.C = 1ull << shift;
+    g.limit = capacity + slack;
+    g.c0 = g.target >> shift;
+    const unsigned long long c_end = umin64(chunks, (g.limit + g.C - 1) >> shift);
+    g.nd = (g.target && c_end > g.c0) ? c_end - g.c0 : 0ull;
+    g.P = g.target ? umin64(listed, partial_cap) : 0ull;
+    return g;
 }
 
-// One item of a launch, as the host reads it back: its true pair count, the
-// chunks handed out, its partial-chunk list (n_partials entries from
-// partial_at in the packed list; only items that stored pairs have one) and
-// its output layout.
-struct ItemPlan {
-    unsigned long long count, chunks, n_partials, partial_at;
-    unsigned long long capacity, slack, out_offset, slack_off;
-    uint32_t shift;
-};
+// first position and length of the hole of partial entry (chunk c, fill f)
+HRR_HD unsigned long long hole_lo(const CompactGeom& g, unsigned long long c, unsigned long long f) {
+    return c * g.C + f;
+}
+HRR_HD unsigned long long hole_len(const CompactGeom& g, unsigned long long c, unsigned long long f) {
+    const unsigned long long lo = c * g.C + f, hi = umin64((c + 1) * g.C, g.target);
+    return hi > lo ? hi - lo : 0ull;
+}
 
-// Plans the moves of every item of a launch: appends their segments to
-// `segments` in item order and sets stored[k] = min(count, capacity) minus the
-// positions left unfilled.  With eight or more items and 8192 or more partial
-// entries the items are cut into up to max_threads contiguous ranges of about
-// equal partial counts, planned on host threads with scratch of their own and
-// joined in item order, so the result equals the one-thread plan.  Returns
-// true when some item left positions unfilled.
-inline bool plan_items(const ItemPlan* items, size_t n, const unsigned long long* partials, unsigned max_threads,
-                       CompactScratch& scratch, std::vector<unsigned long long>& segments,
-                       unsigned long long* stored) {
-    auto plan_range = [&](size_t k0, size_t k1, CompactScratch& sc, std::vector<unsigned long long>& seg) {
-        bool lost = false;
-        for (size_t k = k0; k < k1; ++k) {
-            const ItemPlan& it = items[k];
-            const unsigned long long target = std::min(it.count, it.capacity);
-            stored[k] = 0;
-            if (target == 0) continue;
-            const unsigned long long unfilled =
-                plan_compaction(target, it.chunks, it.shift, it.capacity, it.slack, partials + 2 * it.partial_at,
-                                it.n_partials, it.out_offset, it.slack_off, sc, seg);
-            stored[k] = target - unfilled;
-            if (unfilled) lost = true;
-        }
-        return lost;
-    };
-    unsigned long long total = 0;
-    for (size_t k = 0; k < n; ++k)
-        if (std::min(items[k].count, items[k].capacity)) total += items[k].n_partials;
-    const size_t n_threads =
-        (n >= 8 && total >= 8192) ? std::min<size_t>(std::max(1u, max_threads), std::min<size_t>(8, n)) : 1;
-    if (n_threads <= 1) return plan_range(0, n, scratch, segments);
-    std::vector<size_t> cut(n_threads + 1, n);
-    cut[0] = 0;
-    size_t t = 1;
-    unsigned long long acc = 0;
-    for (size_t k = 0; k < n && t < n_threads; ++k) {
-        if (std::min(items[k].count, items[k].capacity)) acc += items[k].n_partials;
-        if (acc * n_threads >= total * t) cut[t++] = k + 1;
+// first position and length of the stored pairs of data chunk c0 + i with fill `fill`
+HRR_HD unsigned long long data_lo(const CompactGeom& g, unsigned long long i) {
+    return umax64((g.c0 + i) * g.C, g.target);
+}
+HRR_HD unsigned long long data_len(const CompactGeom& g, unsigned long long i, unsigned long long fill) {
+    const unsigned long long lo = data_lo(g, i), hi = umin64((g.c0 + i) * g.C + fill, g.limit);
+    return hi > lo ? hi - lo : 0ull;
+}
+
+// Largest q in [0, n) with prefix[q] <= e, for a nondecreasing prefix with
+// prefix[0] = 0 <= e.
+HRR_HD unsigned long long prefix_rank(const unsigned long long* prefix, unsigned long long n, unsigned long long e) {
+    unsigned long long lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const unsigned long long mid = lo + (hi - lo) / 2;
+        if (prefix[mid] <= e) lo = mid; else hi = mid;
     }
-    std::vector<CompactScratch> sc(n_threads - 1);
-    std::vector<std::vector<unsigned long long>> seg(n_threads - 1);
-    std::vector<char> lost(n_threads, 0);
-    std::vector<std::thread> pool;
-    for (size_t q = 1; q < n_threads; ++q)
-        pool.emplace_back([&, q] { lost[q] = plan_range(cut[q], cut[q + 1], sc[q - 1], seg[q - 1]); });
-    lost[0] = plan_range(cut[0], cut[1], scratch, segments);
-    for (auto& th : pool) th.join();
-    bool any = lost[0] != 0;
-    for (size_t q = 1; q < n_threads; ++q) {
-        any = any || lost[q];
-        segments.insert(segments.end(), seg[q - 1].begin(), seg[q - 1].end());
-    }
-    return any;
+    return lo;
 }
 
 }  // namespace hrr

@@ -11,7 +11,6 @@
 
 #include "../../include/hrr.h"
 #include "hrr_build.hpp"
-#include "hrr_compact.hpp"
 #include "hrr_types.hpp"
 
 struct hrr_hierarchy {
@@ -58,26 +57,22 @@ struct HostItem {
     uint64_t out_offset, out_capacity;
 };
 
-// Host copy of what finish_items needs per item of a launch.
+// Host copy of one item's output layout in a launch.
 struct ItemMeta {
-    unsigned long long out_offset, capacity, slack, slack_off, partial_off;
+    unsigned long long out_offset, capacity, slack, slack_off, partial_off, plan_off;
     uint32_t partial_cap, chunk_shift;
 };
 
 // Per-launch device scratch: one set per stream slot so that concurrent
 // launches (the server) never share queue heads or counters.
 struct LaunchScratch {
-    DevBuf items, task_begin, counters, misc, spill, partials, packed, slack_pairs, slack_weights, segments;
+    DevBuf items, task_begin, counters, misc, spill, partials, plan, slack_pairs, slack_weights;
     DevBuf order_keys, order_idx, order_hist, order_items, order_vbegin, queues;
     std::vector<ItemDesc> h_items;
     std::vector<uint32_t> h_task_begin;
     std::vector<unsigned long long> h_partial_off;   // per item, first entry in `partials`
     unsigned long long* h_pinned = nullptr;          // pinned staging / readback area
     size_t h_pinned_n = 0;
-    unsigned long long* h_partials = nullptr;         // pinned host copy for hole filling
-    size_t h_partials_n = 0;
-    std::vector<unsigned long long> h_segments;
-    CompactScratch compact;                           // scratch of the compaction plan
     std::vector<ItemMeta> meta;
     size_t n_items = 0;
     bool with_weights = false;
@@ -123,16 +118,16 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
                    uint32_t* epw, uint32_t* cap);
 
 // Enqueue one persistent launch of a set of items on `stream` with scratch
-// `S`, and the readback of its counters.  After the stream has been
-// synchronised, finish_items() moves pairs into the holes left by partly
-// filled output chunks (a second small launch, synchronised inside) and fills
-// S.counts / S.stored / S.error / S.stat.
+// `S`: the eye order, the traversal, the compaction that makes every item's
+// stored pairs dense (on the device), and the readback of the counters.
+// After the stream has been synchronised, finish_items() fills S.counts /
+// S.stored / S.error / S.stat from that readback.
 hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostItem>& items, uint32_t epw,
                         uint32_t cap, uint32_t method, uint32_t n_samples, uint32_t psi_s0, bool stats,
                         bool reorder, uint32_t* pairs, float* weights, hipStream_t stream, bool timing = false);
 // Duration of the last timed traversal kernel of S (after the stream has synchronised), ms.
 double timed_kernel_ms(LaunchScratch& S);
-hrr_status finish_items(hrr_ctx* ctx, LaunchScratch& S, uint32_t* pairs, float* weights, hipStream_t stream);
+hrr_status finish_items(hrr_ctx* ctx, LaunchScratch& S);
 
 void release_scratch(LaunchScratch& S);
 

@@ -8,10 +8,10 @@
 //                    from eight per-XCD work queues and cull every eye's pairs
 //                    by a top-down walk of its item's light hierarchy
 //                    (Section 1).
-//   around it        the eye order (bucket keys, a multi-block scan, scatter),
-//                    the packing of the partly filled output chunks after a
-//                    traversal, and the moves that make every item's output
-//                    dense (move_pairs_kernel).
+//   around it        the eye order (bucket keys, a multi-block scan, scatter)
+//                    and the compaction that makes every item's output dense
+//                    after a traversal (compact_plan_kernel,
+//                    compact_move_kernel).
 //
 // Wavefront design.  One wave owns a group of 1..8 eyes.  Its stack of
 // pending hierarchy nodes lives in LDS and is shared by the 64 lanes: each
@@ -32,6 +32,7 @@
 // a one-light leaf's test is bit-identical to the all-pairs definition.
 #include <hip/hip_runtime.h>
 
+#include "hrr_compact.hpp"
 #include "hrr_rmq.hpp"
 #include "hrr_types.hpp"
 
@@ -930,63 +931,117 @@ __global__ __launch_bounds__(256) void order_scatter_kernel(const uint32_t* __re
     }
 }
 
-// After a traversal: pack every item's list of partly filled chunks into
-// one array (items in the order of the item table), so that the host reads
-// all of them with a single copy.  An item's list counts only when it stored
-// pairs (min(count, capacity) > 0), as the host's compaction plan assumes;
-// the packed offset of item k goes to its counter line (CNT_PACKED).  One
-// block; n <= 1024 items.
-__global__ __launch_bounds__(1024) void pack_partials_kernel(const ItemDesc* __restrict__ items, uint32_t n,
-                                                             unsigned long long* __restrict__ packed) {
-    __shared__ unsigned long long cnt[1024], off[1024];
+// Output compaction after a traversal (the arithmetic and its bounds are in
+// hrr_compact.hpp).  compact_plan_kernel, one block per item: the exclusive
+// prefix sums of the hole lengths (partial-list order) and of the data
+// lengths (chunk order) into the item's plan scratch, then the moved count,
+// the dense count and the number of data chunks into its counter line.
+// compact_move_kernel, a grid of blocks per item: moved element e goes from
+// the e-th data position to the e-th hole position.
+
+// Exclusive scan of one value per thread over a block of 256; total = the sum.
+__device__ __forceinline__ unsigned long long block_exclusive_scan_u64(unsigned long long x,
+                                                                       unsigned long long* lds,
+                                                                       unsigned long long& total) {
     const uint32_t t = threadIdx.x;
-    unsigned long long P = 0;
-    if (t < n) {
-        const ItemDesc& D = items[t];
-        const unsigned long long pairs = D.counters[CNT_PAIRS];
-        const unsigned long long listed = D.counters[CNT_PARTIALS];
-        const unsigned long long cap = D.partial_cap;
-        P = (pairs < D.capacity ? pairs : D.capacity) ? (listed < cap ? listed : cap) : 0ull;
-    }
-    cnt[t] = P;
-    off[t] = P;
+    lds[t] = x;
     __syncthreads();
-    for (uint32_t d = 1; d < 1024u; d <<= 1) {
-        const unsigned long long add = t >= d ? off[t - d] : 0ull;
+    for (uint32_t off = 1; off < 256u; off <<= 1) {
+        const unsigned long long add = t >= off ? lds[t - off] : 0ull;
         __syncthreads();
-        off[t] += add;
+        lds[t] += add;
         __syncthreads();
     }
-    off[t] -= P;   // exclusive
-    if (t < n) items[t].counters[CNT_PACKED] = off[t];
+    const unsigned long long incl = lds[t];
+    total = lds[255];
     __syncthreads();
-    for (uint32_t k = 0; k < n; ++k) {
-        const unsigned long long words = 2ull * cnt[k];
-        const unsigned long long* src = items[k].partials;
-        unsigned long long* dst = packed + 2ull * off[k];
-        for (unsigned long long q = t; q < words; q += 1024u) dst[q] = src[q];
+    return incl - x;
+}
+
+__device__ __forceinline__ CompactGeom item_geom(const ItemDesc& D) {
+    const unsigned long long* cnt = D.counters;
+    return compact_geom(cnt[CNT_PAIRS], cnt[CNT_CHUNKS], cnt[CNT_PARTIALS], D.partial_cap, D.capacity, D.slack,
+                        D.chunk_shift);
+}
+
+__global__ __launch_bounds__(256) void compact_plan_kernel(const ItemDesc* __restrict__ items,
+                                                           uint32_t* __restrict__ error) {
+    __shared__ unsigned long long lds[256];
+    const ItemDesc& D = items[blockIdx.x];
+    const CompactGeom g = item_geom(D);
+    const unsigned long long nd_cap = 2ull * D.partial_cap + 2ull;
+    const unsigned long long nd = umin64(g.nd, nd_cap);   // g.nd <= nd_cap always (see the bounds)
+    unsigned long long* Hs = D.plan;
+    unsigned long long* Ds = D.plan + D.partial_cap + 1;
+    const unsigned long long* pl = D.partials;
+
+    unsigned long long run = 0, tot = 0;
+    for (unsigned long long b = 0; b < g.P; b += 256) {
+        const unsigned long long q = b + threadIdx.x;
+        const unsigned long long len = q < g.P ? hole_len(g, pl[2 * q], pl[2 * q + 1]) : 0ull;
+        const unsigned long long ex = block_exclusive_scan_u64(len, lds, tot);
+        if (q < g.P) Hs[q] = run + ex;
+        run += tot;
+    }
+    const unsigned long long TH = run;
+
+    // fills of the data chunks: full, except the partly filled ones (each
+    // chunk is on the partial list at most once)
+    for (unsigned long long i = threadIdx.x; i < nd; i += 256) Ds[i] = g.C;
+    __syncthreads();
+    for (unsigned long long q = threadIdx.x; q < g.P; q += 256) {
+        const unsigned long long c = pl[2 * q];
+        if (c >= g.c0 && c - g.c0 < nd) Ds[c - g.c0] = pl[2 * q + 1];
+    }
+    __syncthreads();
+    run = 0;
+    for (unsigned long long b = 0; b < nd; b += 256) {
+        const unsigned long long i = b + threadIdx.x;
+        const unsigned long long len = i < nd ? data_len(g, i, Ds[i]) : 0ull;
+        const unsigned long long ex = block_exclusive_scan_u64(len, lds, tot);   // every read precedes the writes
+        if (i < nd) Ds[i] = run + ex;
+        run += tot;
+    }
+    const unsigned long long TD = run;
+    if (threadIdx.x == 0) {
+        Hs[g.P] = TH;
+        Ds[nd] = TD;
+        const unsigned long long moved = umin64(TH, TD);
+        D.counters[CNT_MOVED] = moved;
+        D.counters[CNT_ND] = nd;
+        D.counters[CNT_STORED] = g.target - (TH - moved);
+        if (TH > moved || g.nd > nd_cap) atomicOr(error, (uint32_t)ERR_UNFILLED);   // never expected
     }
 }
 
-// Hole filling after a traversal: segment q copies len[q] pairs (and weights)
-// from position src[q] (the caller's buffer, or the slack area when bit 63 is
-// set) to position dst[q] of the caller's buffer.  Sources and destinations
-// never overlap: sources lie at or past an item's final pair count,
-// destinations below it.
-__global__ __launch_bounds__(256) void move_pairs_kernel(const unsigned long long* __restrict__ seg, uint32_t n_seg,
-                                                         uint32_t* pairs, float* weights, const uint32_t* slack_pairs,
-                                                         const float* slack_weights) {
-    constexpr unsigned long long kSlack = 1ull << 63;
-    for (uint32_t q = blockIdx.x; q < n_seg; q += gridDim.x) {
-        const unsigned long long src = seg[3 * q], dst = seg[3 * q + 1], len = seg[3 * q + 2];
-        const bool from_slack = (src & kSlack) != 0;
-        const unsigned long long s0 = src & ~kSlack;
-        const uint2* sp = reinterpret_cast<const uint2*>(from_slack ? slack_pairs : pairs) + s0;
-        const float* sw = weights ? (from_slack ? slack_weights : weights) + s0 : nullptr;
-        uint2* dp = reinterpret_cast<uint2*>(pairs) + dst;
-        for (unsigned long long t = threadIdx.x; t < len; t += blockDim.x) {
-            dp[t] = sp[t];
-            if (weights) weights[dst + t] = sw[t];
+constexpr uint32_t kMoveRun = 16;   // moved elements per thread and step
+
+__global__ __launch_bounds__(256) void compact_move_kernel(const ItemDesc* __restrict__ items) {
+    const ItemDesc& D = items[blockIdx.y];
+    const unsigned long long moved = D.counters[CNT_MOVED];
+    if (moved == 0) return;
+    const CompactGeom g = item_geom(D);
+    const unsigned long long nd = D.counters[CNT_ND];
+    const unsigned long long* Hs = D.plan;
+    const unsigned long long* Ds = D.plan + D.partial_cap + 1;
+    const unsigned long long* pl = D.partials;
+    uint2* out = reinterpret_cast<uint2*>(D.pairs);
+    const uint2* sl = reinterpret_cast<const uint2*>(D.slack_pairs);
+    const unsigned long long cap = D.capacity;
+    const unsigned long long step = (unsigned long long)gridDim.x * blockDim.x * kMoveRun;
+    for (unsigned long long e0 = ((unsigned long long)blockIdx.x * blockDim.x + threadIdx.x) * kMoveRun; e0 < moved;
+         e0 += step) {
+        // moved < both totals, so the walks below stop inside the prefixes
+        unsigned long long q = prefix_rank(Hs, g.P, e0);
+        unsigned long long i = prefix_rank(Ds, nd, e0);
+        const unsigned long long e1 = umin64(e0 + kMoveRun, moved);
+        for (unsigned long long e = e0; e < e1; ++e) {
+            while (Hs[q + 1] <= e) ++q;
+            while (Ds[i + 1] <= e) ++i;
+            const unsigned long long dst = hole_lo(g, pl[2 * q], pl[2 * q + 1]) + (e - Hs[q]);
+            const unsigned long long src = data_lo(g, i) + (e - Ds[i]);
+            out[dst] = src < cap ? out[src] : sl[src - cap];
+            if (D.weights) D.weights[dst] = src < cap ? D.weights[src] : D.slack_weights[src - cap];
         }
     }
 }
@@ -1024,23 +1079,16 @@ extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const
     return hipGetLastError();
 }
 
-// Pack the items' partial-chunk lists (see pack_partials_kernel); packed
-// must hold 2 words per partial-list entry of every item.
-extern "C" hipError_t hrr_launch_pack_partials(const hrr::ItemDesc* items, uint32_t n_items,
-                                               unsigned long long* packed, hipStream_t stream) {
+// Compaction of a launch's items (see compact_plan_kernel): n_items <= 65535.
+extern "C" hipError_t hrr_launch_compact(const hrr::ItemDesc* items, uint32_t n_items, uint32_t* error,
+                                         hipStream_t stream) {
     if (n_items == 0) return hipSuccess;
-    if (n_items > 1024u) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(hrr::pack_partials_kernel, dim3(1), dim3(1024), 0, stream, items, n_items, packed);
-    return hipGetLastError();
-}
-
-extern "C" hipError_t hrr_launch_move_pairs(const unsigned long long* seg, uint32_t n_seg, uint32_t* pairs,
-                                            float* weights, const uint32_t* slack_pairs, const float* slack_weights,
-                                            hipStream_t stream) {
-    if (n_seg == 0) return hipSuccess;
-    const uint32_t blocks = n_seg < 4096u ? n_seg : 4096u;
-    hipLaunchKernelGGL(hrr::move_pairs_kernel, dim3(blocks), dim3(256), 0, stream, seg, n_seg, pairs, weights,
-                       slack_pairs, slack_weights);
+    if (n_items > 65535u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(hrr::compact_plan_kernel, dim3(n_items), dim3(256), 0, stream, items, error);
+    // about 8192 blocks in all, at least 16 and at most 4096 per item
+    uint32_t per_item = 8192u / n_items;
+    per_item = per_item < 16u ? 16u : (per_item > 4096u ? 4096u : per_item);
+    hipLaunchKernelGGL(hrr::compact_move_kernel, dim3(per_item, n_items), dim3(256), 0, stream, items);
     return hipGetLastError();
 }
 

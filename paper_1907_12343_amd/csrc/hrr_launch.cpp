@@ -6,7 +6,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <thread>
 #include <vector>
 
 #include "hrr_compact.hpp"
@@ -22,11 +21,8 @@ extern "C" hipError_t hrr_launch_order(const hrr::OrderItem* items, const uint32
                                        uint32_t total, uint32_t bits, uint32_t rbits, const uint32_t* tile,
                                        uint32_t tile_tz, uint32_t* keys, uint32_t* hist, uint32_t* order, int n_cu,
                                        hipStream_t stream);
-extern "C" hipError_t hrr_launch_pack_partials(const hrr::ItemDesc* items, uint32_t n_items,
-                                               unsigned long long* packed, hipStream_t stream);
-extern "C" hipError_t hrr_launch_move_pairs(const unsigned long long* seg, uint32_t n_seg, uint32_t* pairs,
-                                            float* weights, const uint32_t* slack_pairs, const float* slack_weights,
-                                            hipStream_t stream);
+extern "C" hipError_t hrr_launch_compact(const hrr::ItemDesc* items, uint32_t n_items, uint32_t* error,
+                                         hipStream_t stream);
 
 namespace hrr {
 
@@ -102,7 +98,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     // ---- per-item output chunks, slack and partial lists ----
     std::vector<ItemMeta>& M = S.meta;
     M.assign(n, ItemMeta{});
-    unsigned long long slack_total = 0, partial_total = 0;
+    unsigned long long slack_total = 0, partial_total = 0, plan_total = 0;
     // Queue layout.  Launches of several items with 2^19 or more tasks use
     // interleaved chunks of 2^13 tasks (queue q owns chunks q, q + 8, ...):
     // all XCDs then work on the same heavy items at a time and the Infinity
@@ -137,6 +133,8 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         m.partial_cap = (uint32_t)pk;
         m.partial_off = partial_total;
         partial_total += pk;
+        m.plan_off = plan_total;
+        plan_total += 3 * pk + 4;   // hole prefixes pk + 1, data prefixes 2 pk + 3
     }
 
     // ---- eye processing order: counting sort by (item, Morton cell) ----
@@ -199,8 +197,8 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     if ((e = S.misc.ensure(16 * sizeof(unsigned long long))) != hipSuccess) return hip_fail(e, "misc");
     if ((e = S.partials.ensure(std::max<unsigned long long>(partial_total, 1) * 2 * sizeof(unsigned long long))) != hipSuccess)
         return hip_fail(e, "partial-chunk list");
-    if ((e = S.packed.ensure(std::max<unsigned long long>(partial_total, 1) * 2 * sizeof(unsigned long long))) != hipSuccess)
-        return hip_fail(e, "packed partial-chunk list");
+    if ((e = S.plan.ensure(std::max<unsigned long long>(plan_total, 1) * sizeof(unsigned long long))) != hipSuccess)
+        return hip_fail(e, "compaction plan");
     if ((e = S.slack_pairs.ensure(std::max<unsigned long long>(slack_total, 1) * 2 * sizeof(uint32_t))) != hipSuccess)
         return hip_fail(e, "output slack");
     if (with_w && (e = S.slack_weights.ensure(std::max<unsigned long long>(slack_total, 1) * sizeof(float))) != hipSuccess)
@@ -268,6 +266,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         D.order = ordered ? static_cast<const uint32_t*>(S.order_idx.p) + vbegin[k] : nullptr;
         D.counters = d_counters + k * CNT_STRIDE;
         D.partials = d_partials + 2 * m.partial_off;
+        D.plan = static_cast<unsigned long long*>(S.plan.p) + m.plan_off;
         D.capacity = it.out_capacity;
         D.slack = m.slack;
         D.partial_cap = m.partial_cap;
@@ -377,9 +376,13 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
             if ((e = hipEventRecord(S.ev_end, stream)) != hipSuccess) return hip_fail(e, "timing event");
             S.timed = true;
         }
-        if ((e = hrr_launch_pack_partials(static_cast<const ItemDesc*>(S.items.p), (uint32_t)n,
-                                          static_cast<unsigned long long*>(S.packed.p), stream)) != hipSuccess)
-            return hip_fail(e, "pack partial chunks");
+        // make every item's stored pairs dense (on the device, before the readback)
+        bool any_capacity = false;
+        for (size_t k = 0; k < n; ++k) any_capacity = any_capacity || items[k].out_capacity > 0;
+        if (any_capacity &&
+            (e = hrr_launch_compact(static_cast<const ItemDesc*>(S.items.p), (uint32_t)n, A.error, stream)) !=
+                hipSuccess)
+            return hip_fail(e, "output compaction");
     }
     if ((e = hipMemcpyAsync(S.h_pinned, d_counters, n * CNT_STRIDE * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                             stream)) != hipSuccess)
@@ -397,82 +400,16 @@ double timed_kernel_ms(LaunchScratch& S) {
     return (double)ms;
 }
 
-hrr_status finish_items(hrr_ctx*, LaunchScratch& S, uint32_t* pairs, float* weights, hipStream_t stream) {
+hrr_status finish_items(hrr_ctx*, LaunchScratch& S) {
     const size_t n = S.n_items;
-    const std::vector<ItemMeta>& M = S.meta;
     S.counts.assign(n, 0);
     S.stored.assign(n, 0);
     const unsigned long long* rd = S.h_pinned;
     S.error = (uint32_t)rd[n * CNT_STRIDE];
     for (int q = 0; q < ST_N; ++q) S.stat[q] = rd[n * CNT_STRIDE + 1 + q];
-    if (S.error) return HRR_OK;   // caller reports
-
-    hipError_t e;
-    S.h_segments.clear();
-    // The lists of partly filled chunks were packed on the device (items with
-    // stored pairs only, packed offset in CNT_PACKED): read them with one copy.
-    std::vector<size_t> part_at(n, 0);
-    size_t total = 0;
     for (size_t k = 0; k < n; ++k) {
-        const unsigned long long cnt = rd[k * CNT_STRIDE + CNT_PAIRS];
-        const unsigned long long P = std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], M[k].partial_cap);
-        if (std::min(cnt, M[k].capacity)) total += (size_t)P;
-        part_at[k] = (size_t)rd[k * CNT_STRIDE + CNT_PACKED];
-    }
-    for (size_t k = 0; k < n; ++k) {
-        const unsigned long long cnt = rd[k * CNT_STRIDE + CNT_PAIRS];
-        const unsigned long long P = std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], M[k].partial_cap);
-        if (std::min(cnt, M[k].capacity) && part_at[k] + P > total)
-            return fail(HRR_E_DEVICE, "item %zu: packed partial-chunk list out of range", k);
-    }
-    if (total) {
-        if (S.h_partials_n < 2 * total) {
-            if (S.h_partials) (void)hipHostFree(S.h_partials);
-            S.h_partials = nullptr;
-            S.h_partials_n = 0;
-            const size_t want = 2 * total + total / 2;   // some headroom
-            if ((e = hipHostMalloc((void**)&S.h_partials, want * sizeof(unsigned long long), hipHostMallocDefault)) !=
-                hipSuccess)
-                return hip_fail(e, "pinned partial-chunk copy");
-            S.h_partials_n = want;
-        }
-        if ((e = hipMemcpyAsync(S.h_partials, S.packed.p, 2 * total * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                stream)) != hipSuccess)
-            return hip_fail(e, "read partial chunks");
-        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "read partial chunks");
-    }
-    // Plan every item's moves (on several host threads for launches with many
-    // partial chunks: many items, each touched by most waves).
-    std::vector<ItemPlan> plan(n);
-    for (size_t k = 0; k < n; ++k) {
-        const ItemMeta& m = M[k];
-        ItemPlan& p = plan[k];
-        p.count = rd[k * CNT_STRIDE + CNT_PAIRS];
-        p.chunks = rd[k * CNT_STRIDE + CNT_CHUNKS];
-        p.n_partials = std::min<unsigned long long>(rd[k * CNT_STRIDE + CNT_PARTIALS], m.partial_cap);
-        p.partial_at = part_at[k];
-        p.capacity = m.capacity;
-        p.slack = m.slack;
-        p.out_offset = m.out_offset;
-        p.slack_off = m.slack_off;
-        p.shift = m.chunk_shift;
-        S.counts[k] = p.count;
-    }
-    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-    if (plan_items(plan.data(), n, S.h_partials, std::min(8u, hw), S.compact, S.h_segments, S.stored.data()))
-        S.error |= ERR_UNFILLED;   // pairs lost: never expected
-    const size_t n_seg = S.h_segments.size() / 3;
-    if (n_seg) {
-        if ((e = S.segments.ensure(S.h_segments.size() * sizeof(unsigned long long))) != hipSuccess)
-            return hip_fail(e, "segments");
-        if ((e = hipMemcpyAsync(S.segments.p, S.h_segments.data(), S.h_segments.size() * sizeof(unsigned long long),
-                                hipMemcpyHostToDevice, stream)) != hipSuccess)
-            return hip_fail(e, "upload segments");
-        if ((e = hrr_launch_move_pairs(static_cast<const unsigned long long*>(S.segments.p), (uint32_t)n_seg, pairs,
-                                       weights, static_cast<const uint32_t*>(S.slack_pairs.p),
-                                       static_cast<const float*>(S.slack_weights.p), stream)) != hipSuccess)
-            return hip_fail(e, "hole filling");
-        if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "hole filling");
+        S.counts[k] = rd[k * CNT_STRIDE + CNT_PAIRS];
+        S.stored[k] = rd[k * CNT_STRIDE + CNT_STORED];
     }
     return HRR_OK;
 }

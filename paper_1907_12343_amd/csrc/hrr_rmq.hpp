@@ -52,10 +52,12 @@
 
 #include <stdint.h>
 
+#ifndef HRR_HD
 #if defined(__HIPCC__)
 #define HRR_HD __host__ __device__ __forceinline__
 #else
 #define HRR_HD inline
+#endif
 #endif
 
 namespace hrr {

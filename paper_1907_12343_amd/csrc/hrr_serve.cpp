@@ -212,7 +212,7 @@ hrr_status run_batch(Server& sv, Slot& slot, const std::vector<ReqPtr>& batch) {
                                  slot.stream);
     if (st != HRR_OK) return st;
     if ((e = hipStreamSynchronize(slot.stream)) != hipSuccess) return hip_fail(e, "server traversal");
-    if ((st = finish_items(ctx, slot.S, pairs, nullptr, slot.stream)) != HRR_OK) return st;
+    if ((st = finish_items(ctx, slot.S)) != HRR_OK) return st;
     if (slot.S.error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", slot.S.error);
     return HRR_OK;
 }

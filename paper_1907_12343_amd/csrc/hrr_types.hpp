@@ -38,8 +38,9 @@ struct ItemDesc {
     uint32_t* slack_pairs;        // positions >= capacity land here (library memory)
     float* slack_weights;
     const uint32_t* order;        // processing order of the virtual eyes, or null (index order)
-    unsigned long long* counters; // CNT_PAIRS, CNT_CHUNKS, CNT_PARTIALS, CNT_PACKED (device)
+    unsigned long long* counters; // CNT_* (device)
     unsigned long long* partials; // (chunk, fill) of partly filled chunks
+    unsigned long long* plan;     // compaction prefixes: partial_cap + 1 hole, 2 partial_cap + 3 data entries
     unsigned long long capacity;  // pairs the slice can hold
     unsigned long long slack;     // pairs the slack area can hold
     uint32_t partial_cap, chunk_shift;
@@ -66,7 +67,11 @@ struct OrderItem {
 };
 
 // Per-item device counters, one 128-byte line per item.
-enum CounterIdx { CNT_PAIRS = 0, CNT_CHUNKS = 1, CNT_PARTIALS = 2, CNT_PACKED = 3, CNT_STRIDE = 16 };
+// CNT_STORED / CNT_MOVED / CNT_ND are written by the compaction after the
+// traversal: pairs dense at the front of the slice, pairs moved, data chunks.
+enum CounterIdx {
+    CNT_PAIRS = 0, CNT_CHUNKS = 1, CNT_PARTIALS = 2, CNT_STORED = 3, CNT_MOVED = 4, CNT_ND = 5, CNT_STRIDE = 16
+};
 
 // Kernel arguments of the persistent traversal launch.
 struct TravArgs {

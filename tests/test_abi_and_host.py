@@ -355,16 +355,48 @@ int main(int argc, char** argv) {
         x.fill += b;
         if (x.fill >= C) { x.fill -= C; x.chunk = next; if (x.fill == 0) x.chunk = -1; }
     }
-    const unsigned long long target = std::min(count, cap);
-    hrr::CompactScratch scratch;
-    std::vector<unsigned long long> seg;
-    const unsigned long long unfilled = hrr::plan_compaction(target, K, shift, cap, slack, partials.data(),
-                                                             partials.size() / 2, 0, 0, scratch, seg);
-    // moves read sources that are never destinations, so order does not matter
-    for (size_t s = 0; s < seg.size(); s += 3) {
-        const unsigned long long src = seg[s], dst = seg[s + 1], len = seg[s + 2];
-        for (unsigned long long q = 0; q < len; ++q)
-            buf[dst + q] = (src & hrr::kSlackFlag) ? sl[(src & ~hrr::kSlackFlag) + q] : buf[src + q];
+    // the device compaction (compact_plan_kernel, then compact_move_kernel),
+    // emulated with the functions those kernels use
+    const unsigned long long listed = partials.size() / 2;
+    const hrr::CompactGeom g = hrr::compact_geom(count, K, listed, pcap, cap, slack, shift);
+    const unsigned long long target = g.target;
+    if (g.nd > 2 * pcap + 2) {
+        printf("data chunks %llu above the bound %llu\n", g.nd, 2 * pcap + 2);
+        return 1;
+    }
+    std::vector<unsigned long long> Hs(g.P + 1), Ds(g.nd + 1), fill(g.nd, C);
+    unsigned long long run = 0;
+    for (unsigned long long q = 0; q < g.P; ++q) {
+        Hs[q] = run;
+        run += hrr::hole_len(g, partials[2 * q], partials[2 * q + 1]);
+    }
+    Hs[g.P] = run;
+    for (unsigned long long q = 0; q < g.P; ++q) {
+        const unsigned long long c = partials[2 * q];
+        if (c >= g.c0 && c - g.c0 < g.nd) fill[c - g.c0] = partials[2 * q + 1];
+    }
+    run = 0;
+    for (unsigned long long i = 0; i < g.nd; ++i) {
+        Ds[i] = run;
+        run += hrr::data_len(g, i, fill[i]);
+    }
+    Ds[g.nd] = run;
+    const unsigned long long moved = std::min(Hs[g.P], Ds[g.nd]);
+    const unsigned long long unfilled = Hs[g.P] - moved;
+    // element e: from the e-th data position to the e-th hole position (sources
+    // are never destinations, so the order of the moves does not matter)
+    for (unsigned long long e = 0; e < moved; ++e) {
+        unsigned long long q = hrr::prefix_rank(Hs.data(), g.P, e);
+        unsigned long long i = hrr::prefix_rank(Ds.data(), g.nd, e);
+        while (Hs[q + 1] <= e) ++q;
+        while (Ds[i + 1] <= e) ++i;
+        const unsigned long long dst = hrr::hole_lo(g, partials[2 * q], partials[2 * q + 1]) + (e - Hs[q]);
+        const unsigned long long src = hrr::data_lo(g, i) + (e - Ds[i]);
+        if (dst >= target || src < target || src >= cap + slack) {
+            printf("move out of place: %llu -> %llu\n", src, dst);
+            return 1;
+        }
+        buf[dst] = src < cap ? buf[src] : sl[src - cap];
     }
     std::set<long long> seen;
     for (unsigned long long p = 0; p < target; ++p) {
@@ -373,80 +405,10 @@ int main(int argc, char** argv) {
             return 1;
         }
     }
-    printf("ok unfilled=%llu segments=%zu partials=%zu chunks=%llu\n", unfilled, seg.size() / 3, partials.size() / 2, K);
+    printf("ok unfilled=%llu moved=%llu partials=%zu chunks=%llu\n", unfilled, moved, partials.size() / 2, K);
     return unfilled ? 1 : 0;
 }
 """
-
-
-PLAN_ITEMS_HARNESS = r"""
-#include <cstdio>
-#include <cstdlib>
-#include <random>
-#include <vector>
-#include "hrr_compact.hpp"
-// Random launches of many items (random partial-chunk lists, capacities below,
-// equal to and above the counts, empty items); plan_items on 1 and on 8
-// threads must give the same segments, stored counts and unfilled flag.
-// args: items partials_per_item seed
-int main(int argc, char** argv) {
-    const size_t n = strtoull(argv[1], 0, 10);
-    const unsigned long long per = strtoull(argv[2], 0, 10);
-    std::mt19937_64 rng(strtoull(argv[3], 0, 10));
-    std::vector<hrr::ItemPlan> items(n);
-    std::vector<unsigned long long> partials;
-    unsigned long long off = 0;
-    for (size_t k = 0; k < n; ++k) {
-        hrr::ItemPlan& it = items[k];
-        it.shift = 7 + (unsigned)(rng() % 7);
-        const unsigned long long C = 1ull << it.shift;
-        const unsigned long long P = rng() % (2 * per + 1);
-        it.count = (k % 9 == 4) ? 0 : P * C / 2 + rng() % (64 * C);
-        const int mode = (int)(rng() % 3);
-        it.capacity = mode == 0 ? it.count : mode == 1 ? it.count / 2 : it.count + rng() % 1000;
-        it.chunks = it.count / C + P + 1;
-        it.slack = 2 * P * C;
-        it.n_partials = it.count ? P : 0;
-        it.partial_at = partials.size() / 2;
-        it.out_offset = off;
-        it.slack_off = off;
-        off += it.capacity + it.slack;
-        for (unsigned long long q = 0; q < it.n_partials; ++q) {
-            partials.push_back(rng() % it.chunks);
-            partials.push_back(rng() % C);
-        }
-    }
-    std::vector<unsigned long long> s1, s8, st1(n), st8(n);
-    hrr::CompactScratch c1, c8;
-    const bool l1 = hrr::plan_items(items.data(), n, partials.data(), 1, c1, s1, st1.data());
-    const bool l8 = hrr::plan_items(items.data(), n, partials.data(), 8, c8, s8, st8.data());
-    if (l1 != l8 || s1 != s8 || st1 != st8) { printf("mismatch\n"); return 1; }
-    printf("ok segments=%zu partials=%zu\n", s1.size() / 3, partials.size() / 2);
-    return 0;
-}
-"""
-
-
-@pytest.fixture(scope="module")
-def plan_items_harness(tmp_path_factory):
-    d = tmp_path_factory.mktemp("plan_items")
-    src = d / "plan_items.cpp"
-    src.write_text(PLAN_ITEMS_HARNESS)
-    exe = d / "plan_items"
-    subprocess.run(["g++", "-O2", "-std=c++17", "-pthread", "-I", CSRC, str(src), "-o", str(exe)],
-                   check=True)
-    return str(exe)
-
-
-@pytest.mark.parametrize("items,per,seed", [(3, 100, 1), (8, 2000, 2), (40, 400, 3), (256, 900, 4),
-                                            (1000, 20, 5)])
-def test_threaded_compaction_plan_equals_one_thread(plan_items_harness, items, per, seed):
-    """Many-item launches plan their hole filling on host threads over item
-    ranges; the joined plan must equal the one-thread plan exactly."""
-    out = subprocess.run([plan_items_harness, str(items), str(per), str(seed)], capture_output=True,
-                         text=True)
-    assert out.returncode == 0, out.stdout + out.stderr
-    assert out.stdout.startswith("ok")
 
 
 @pytest.fixture(scope="module")
