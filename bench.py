@@ -61,8 +61,9 @@ def frame_workload(args):
     import paper_1907_12343_amd as hrr
     import synth
 
-    fr = synth.frame()
-    ns = max(1, args.samples)
+    tiny = args.workload == "tiny"
+    fr = synth.tiny() if tiny else synth.frame()
+    ns = 1 if tiny else max(1, args.samples)
     if ns > 1:
         # several samples per eye (Section 3): the first 1080 / N pixel rows,
         # so that eyes x samples stays at about one frame of virtual eyes
@@ -129,7 +130,7 @@ def frame_workload(args):
         "vs_baseline": None,
         "dtype": "u32+f32",
         "data": "synthetic",
-        "config": {"workload": _frame_name(ns, args.weights),
+        "config": {"workload": _frame_name(ns, args.weights, tiny),
                    "n_eyes": n_eyes, "n_lights": int(fr["lights"].shape[0]),
                    "rmq": args.rmq, "parallelism": "1 GPU"},
         "pairs_per_s": n / (ms * 1e-3),
@@ -143,7 +144,7 @@ def frame_workload(args):
         "algorithmic_lane_ops": ops,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": _traffic_bytes(args) if (ns == 1 and not args.weights) else None},
+                     "traffic": _traffic_bytes(args) if (ns == 1 and not args.weights and not tiny) else None},
     }
     if ns > 1:
         line["config"]["samples_per_eye"] = ns
@@ -201,9 +202,12 @@ def _traffic_bytes(args, path=TRAFFIC_FILE):
     return (rec["fetch_kib_scaled"] + rec["write_kib_scaled"]) * 1024.0
 
 
-def _frame_name(ns, weights):
+def _frame_name(ns, weights, tiny=False):
     name = "frame: 1920x1080 eyes x 2^20 lights, 64-Gaussian mixture sigma 0.02, s=1e-4, leaf 1"
-    if ns > 1:
+    if tiny:
+        # the small parity case: launch-latency bound, reported for completeness
+        name = "tiny: 4096 uniform eyes (64 wide) x 1024 uniform lights, s=1e-3, leaf 1"
+    elif ns > 1:
         name = ("frame rows 0..%d (1920x%d eyes) x %d samples per eye x 2^20 lights, "
                 "64-Gaussian mixture sigma 0.02, s=1e-4, leaf 1" % (1080 // ns - 1, 1080 // ns, ns))
     if weights:
@@ -226,7 +230,7 @@ def cpu_baseline_frame(fr, n_eyes, args, ns=1):
                        psi_s0=PSI_S0 if ns > 1 else 0, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": sel.size * ns / dt, "unit": "eyes/s", "cores": threads, "kind": "oracle",
-            "sample": "%d eyes%s evenly spaced over the frame, all-pairs test against all %d "
+            "sample": "%d eyes%s evenly spaced over the eye set, all-pairs test against all %d "
                       "lights (%.1f s)" % (sel.size, " x %d samples" % ns if ns > 1 else "",
                                            ls.shape[0], dt)}
 
@@ -526,7 +530,7 @@ def main():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--workload", default="frame",
-                   choices=["frame", "rangemin", "batched", "served"])
+                   choices=["frame", "tiny", "rangemin", "batched", "served"])
     p.add_argument("--requests", type=int, default=300, help="served: requests per load")
     p.add_argument("--budget-gib", type=float, default=64.0, help="served: device arena")
     p.add_argument("--load-seconds", type=float, default=10.0,
@@ -553,7 +557,7 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sharded design is documented, not built)", file=sys.stderr)
         sys.exit(2)
-    fn = {"frame": frame_workload, "rangemin": rangemin_workload,
+    fn = {"frame": frame_workload, "tiny": frame_workload, "rangemin": rangemin_workload,
           "batched": batched_workload, "served": served_workload}[args.workload]
     line = fn(args)
     print(json.dumps(line), flush=True)
