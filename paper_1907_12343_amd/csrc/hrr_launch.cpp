@@ -8,8 +8,8 @@
 #include <algorithm>
 #include <vector>
 
-#include "hrr_compact.hpp"
 #include "hrr_ctx.hpp"
+#include "hrr_layout.hpp"
 
 extern "C" hipError_t hrr_launch_traverse(const hrr::TravArgs* A, uint32_t eyes_per_wave, uint32_t method,
                                           int stats, int with_weights, uint32_t blocks, hipStream_t stream);
@@ -99,30 +99,18 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     std::vector<ItemMeta>& M = S.meta;
     M.assign(n, ItemMeta{});
     unsigned long long slack_total = 0, partial_total = 0, plan_total = 0;
-    // Queue layout.  Launches of several items with 2^19 or more tasks use
-    // interleaved chunks of 2^13 tasks (queue q owns chunks q, q + 8, ...):
-    // all XCDs then work on the same heavy items at a time and the Infinity
-    // Cache holds fewer hierarchies at once (256 caches: kernel 70.3 -> 66.5
-    // ms); other launches use eight contiguous slices of equal cost.
-    const uint32_t il_shift = (n > 1 && tasks >= (1ull << 19)) ? 13u : 0u;
-    // A wave visits each queue once (cyclic order from its own) and takes a
-    // queue's tasks in increasing order, so within one queue visit the items
-    // it meets are nondecreasing and it leaves an item (publishing a partly
-    // filled chunk) at most once.  With contiguous slices the queues are in
-    // task order too: at most twice per item (the one wrap), once in a
-    // one-item launch; with interleaved chunks at most once per queue visit.
-    // Every allocated chunk other than those is full, so the pairs stored past
-    // the capacity (slack) and the holes below it are bounded by partial_cap
-    // chunks each; a slack of twice that lets the compaction fill every hole
-    // below min(count, capacity).
-    const uint64_t leaves_per_wave = il_shift ? kQueues : (n > 1 ? 2 : 1);
+    // Queue layout and the partial-chunk bound (hrr_layout.hpp).  Every
+    // allocated chunk other than the partly filled ones is full, so the pairs
+    // stored past the capacity (slack) and the holes below it are bounded by
+    // partial_cap chunks each; a slack of twice that lets the compaction fill
+    // every hole below min(count, capacity).
+    const uint32_t il_shift = queue_interleave_shift(n, tasks);
+    const uint64_t leaves_per_wave = departures_per_wave(n, il_shift);
     for (size_t k = 0; k < n; ++k) {
         const uint64_t wk = std::max<uint64_t>(1, std::min<uint64_t>(waves, tasks_of[k]));
         const uint64_t pk = std::max<uint64_t>(1, std::min<uint64_t>(leaves_per_wave * waves, tasks_of[k]));
         const unsigned long long capk = items[k].out_capacity;
-        // about sixteen chunks per touching wave, 128..8192 pairs
-        uint32_t shift = kMinChunkShift;
-        while (shift < kMaxChunkShift && (capk >> (shift + 1)) >= 16 * wk) ++shift;
+        const uint32_t shift = chunk_shift_for(capk, wk);
         ItemMeta& m = M[k];
         m.out_offset = items[k].out_offset;
         m.capacity = capk;
@@ -145,24 +133,9 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         vtotal += items[k].h->n_lights ? (uint64_t)items[k].eyes.n * n_samples : 0ull;
     }
     vbegin[n] = (uint32_t)std::min<uint64_t>(vtotal, 0xFFFFFFFFull);
-    // Key: Morton cells of about 2^11 or more virtual eyes each (at least two
-    // bits per axis where the bucket budget allows), then up to 9 bits of the
-    // shift class.  On the 1920x1080 frame over 2^20 lights (3 bits per axis,
-    // 9 class bits) this runs 4-5 % faster than finer cells alone; a launch of
-    // 256 small items is insensitive to the split as long as cells have two
-    // or more bits per axis.
+    // eye order key (hrr_layout.hpp)
     uint32_t bits = 0, rbits = 0;
-    if (reorder && vtotal > 0 && vtotal < 0xFFFFFFFFull) {
-        const uint64_t per_item = std::max<uint64_t>(vtotal / n, 1);
-        while (bits < 2 && ((uint64_t)n << (3 * (bits + 1))) <= kOrderMaxBuckets) ++bits;
-        while (bits && bits < 10 && (per_item >> (3 * (bits + 1))) >= (1u << 11) &&
-               ((uint64_t)n << (3 * (bits + 1))) <= kOrderMaxBuckets)
-            ++bits;
-        if (bits && ctx->tile_bits) {
-            rbits = std::min<uint32_t>(9u, ctx->tile_bits);
-            while (rbits && ((uint64_t)n << (3 * bits + rbits)) > kOrderMaxBuckets) --rbits;
-        }
-    }
+    if (reorder) order_key_bits(n, vtotal, ctx->tile_bits, &bits, &rbits);
     const bool ordered = bits > 0;
     std::vector<OrderItem> oitems;
     if (ordered) {

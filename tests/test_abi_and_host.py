@@ -508,3 +508,76 @@ def test_device_range_minimum_code_on_the_host(orc, rmq_harness):
     want, _ = orc.rmq_scan(a, b, r)
     for m in range(4):
         assert np.array_equal(got[:, m], want.astype(np.uint64)), "method %d" % m
+
+
+LAYOUT_HARNESS = r"""
+#include <cstdio>
+#include "hrr_layout.hpp"
+// stdin lines: "o n virtual_eyes tile_bits" | "q n tasks" | "c capacity waves"
+int main() {
+    char op;
+    unsigned long long a, b, c;
+    while (scanf(" %c", &op) == 1) {
+        if (op == 'o' && scanf("%llu %llu %llu", &a, &b, &c) == 3) {
+            uint32_t bits, rbits;
+            hrr::order_key_bits(a, b, (uint32_t)c, &bits, &rbits);
+            printf("%u %u\n", bits, rbits);
+        } else if (op == 'q' && scanf("%llu %llu", &a, &b) == 2) {
+            const uint32_t s = hrr::queue_interleave_shift(a, b);
+            printf("%u %llu\n", s, (unsigned long long)hrr::departures_per_wave(a, s));
+        } else if (op == 'c' && scanf("%llu %llu", &a, &b) == 2) {
+            printf("%u\n", hrr::chunk_shift_for(a, b));
+        } else {
+            return 1;
+        }
+    }
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def layout_harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("layout")
+    src = d / "layout.cpp"
+    src.write_text(LAYOUT_HARNESS)
+    exe = d / "layout"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+def _ask(exe, lines):
+    out = subprocess.run([exe], input="\n".join(lines) + "\n", capture_output=True, text=True,
+                         check=True).stdout.split("\n")
+    return [tuple(map(int, o.split())) for o in out if o]
+
+
+def test_launch_layout_choices(layout_harness):
+    """Eye-order key widths, queue layout, departures per wave and chunk size
+    of a launch, for the benchmark shapes and the boundaries of each rule."""
+    ask = lambda lines: _ask(layout_harness, lines)
+    # order key: frame (3 bits per axis, 9 class bits), 256 caches (2, 6), a
+    # small item (2, 9), the bucket budget, tiles without class bits
+    assert ask(["o 1 2073600 12", "o 256 4034935 12", "o 1 4096 12", "o 16384 1000000 12",
+                "o 131073 1000000 12", "o 1 2073600 0", "o 1 2073600 3", "o 1 0 12",
+                "o 1 4294967295 12"]) == [
+        (3, 9), (2, 6), (2, 9), (2, 0), (0, 0), (3, 0), (3, 3), (0, 0), (0, 0)]
+    # the budget always holds and cells keep two bits per axis where it allows
+    lines, cases = [], []
+    for n in (1, 2, 3, 7, 64, 255, 1024, 4096, 16383, 16384, 16385, 131072):
+        for ve in (1, 100, 2 ** 11, 2 ** 14, 2 ** 20, 2 ** 24, 2 ** 31):
+            for tb in (0, 1, 12, 32):
+                lines.append("o %d %d %d" % (n, ve, tb))
+                cases.append((n, ve, tb))
+    for (n, ve, tb), (bits, rbits) in zip(cases, ask(lines)):
+        if bits:
+            assert n << (3 * bits + rbits) <= 1 << 20
+            assert rbits <= min(9, tb)
+        assert bits >= min(2, max(b for b in range(3) if n << (3 * b) <= 1 << 20))
+    # queues: interleaved 2^13-task chunks for several items with >= 2^19 tasks
+    assert ask(["q 1 10000000", "q 2 524287", "q 2 524288", "q 256 4034935", "q 1 1"]) == [
+        (0, 1), (0, 2), (13, 8), (13, 8), (0, 1)]
+    # chunks: about sixteen per touching wave, 2^7 .. 2^13 pairs
+    w = 7168
+    assert ask(["c 0 1", "c %d 1" % (1 << 40), "c 4829514196 %d" % w, "c %d %d" % (16 * w * 256, w),
+                "c %d %d" % (16 * w * 256 - 1, w)]) == [(7,), (13,), (13,), (8,), (7,)]
