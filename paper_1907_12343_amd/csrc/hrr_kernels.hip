@@ -331,9 +331,10 @@ __device__ __forceinline__ void stack_refill(StackState& st, const WaveLds& L, c
 // wave takes a whole chunk from the item's chunk counter (one device-scope
 // atomic per chunk instead of one per flush: a single address serialises
 // those atomics) and writes its accepted pairs into it directly from the
-// lanes, compacted with ballot/mbcnt.  Every wave leaves at most one partly
-// filled chunk per item; it records (chunk, fill) so that the host can move
-// the pairs found past the final count into those holes.  Positions at or
+// lanes, compacted with ballot/mbcnt.  A wave leaving an item publishes its
+// partly filled chunk as (chunk, fill) (the launch bounds how often a wave can
+// leave an item), so that the compaction kernels can move the pairs found
+// past the final count into those holes.  Positions at or
 // past the caller's capacity go to a library slack area, positions past that
 // are dropped (the count stays exact).
 constexpr unsigned long long kNoChunk = ~0ull;
