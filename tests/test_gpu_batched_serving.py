@@ -47,6 +47,14 @@ def _plain_keys(ctx, h, eyes_t, s, width, offset=0):
     return pair_keys_from_gpu(pairs)
 
 
+def _pairs_with_weights(pairs, weights):
+    """Sorted (eye, light, weight bits) tuples of a GPU result."""
+    p = pairs.cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    w = weights.cpu().numpy().view(np.uint32).astype(np.int64)
+    order = np.lexsort((p[:, 1], p[:, 0]))
+    return [tuple(x) for x in np.stack([p[order, 0], p[order, 1], w[order]], 1).tolist()]
+
+
 def _small_cache(c, max_lights=1 << 16, max_eyes=1 << 12):
     """Cache c of the batched workload, cut to sizes the oracle samples fast."""
     d = synth.batched_cache(c)
@@ -157,11 +165,12 @@ def test_batched_interleaved_queues_equal_plain_and_oracle(ctx, orc, hrr):
     caps[9] = counts[9] + 777      # room to spare
     offs = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
     pairs = torch.full((int(offs[-1]), 2), -1, dtype=torch.int32, device=ctx.torch_device)
+    weights = torch.full((int(offs[-1]),), -1.0, dtype=torch.float32, device=ctx.torch_device)
     items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=int(offs[k]),
                   out_capacity=int(caps[k]))
              for k, (h, e, d) in enumerate(zip(hs, eyes, caches))]
     with pytest.raises(hrr.OverflowResult) as ei:
-        ctx.traverse_batched(items, pairs)
+        ctx.traverse_batched(items, pairs, weights=weights)
     assert [int(x) for x in ei.value.counts] == counts
     rng = np.random.default_rng(11)
     for k, d in enumerate(caches):
@@ -173,6 +182,11 @@ def test_batched_interleaved_queues_equal_plain_and_oracle(ctx, orc, hrr):
             assert np.isin(keys, full).all()
             continue
         assert np.array_equal(keys, full)
+        # the weights moved with their pairs: (pair, 1/p) tuples equal a plain launch's
+        if k % 3 == 0:
+            pp, _, _, pw = ctx.traverse_all(hs[k], eyes[k], d["s"], d["width"], with_weights=True)
+            got_w = _pairs_with_weights(sl, weights[offs[k]:offs[k] + counts[k]])
+            assert got_w == _pairs_with_weights(pp, pw)
         if k % 6 == 0:
             sel = np.sort(rng.choice(d["eyes"].shape[0], 8, replace=False)).astype(np.uint32)
             want = _oracle_keys(orc, d["lights"], d["eyes"], sel, d["width"], 0, d["s"])
