@@ -47,7 +47,8 @@ OPS_RMQ = 40
 OPS_LEAF = 30
 OPS_PAIR = 6
 BYTES_PER_QUERY = 20   # range minimum: a, b, r in; argmin, min out
-RMQ_METHODS = {"paper": 0, "direct": 1, "paper_full": 2, "paper_loop": 3}
+RMQ_METHODS = {"paper": 0, "direct": 1, "paper_full": 2, "paper_loop": 3, "dyadic": 4,
+               "paper_no_reuse": 5}
 
 
 def _sync_all():
@@ -241,6 +242,8 @@ def rangemin_workload(args):
     import paper_1907_12343_amd as hrr
     import synth
 
+    if args.rmq == "paper_no_reuse":
+        sys.exit("--rmq paper_no_reuse changes the traversal only; range_min has no parent minimum")
     a, b, r = synth.rangemin_queries()
     ctx = hrr.Context(synth.dither_tile(100), device=0)
     dev = "cuda:0"

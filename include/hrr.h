@@ -88,8 +88,9 @@ int hrr_version(void);
 /* Range minimum of the rotated radical inverse                               */
 /* ------------------------------------------------------------------------- */
 
-/* All methods return the same (argmin, min); they differ in how the paper's
- * steps are scheduled on the VALU. */
+/* All methods return the same (argmin, min).  Methods 0-3 differ in how the
+ * paper's steps are scheduled on the VALU; method 4 is a different closed form
+ * kept for comparison. */
 #define HRR_RMQ_PAPER 0u      /* default: the paper's case analysis and sweeps (Section 2, Algorithms 2
                                  and 3) with all candidate flip positions tested at once in bit
                                  arithmetic, then Algorithm 3's refinement of the winning prefix */
@@ -97,6 +98,11 @@ int hrr_version(void);
 #define HRR_RMQ_PAPER_FULL 2u /* ablation: the sweeps as loops, refining every candidate in turn */
 #define HRR_RMQ_PAPER_LOOP 3u /* ablation: the sweeps as loops, refining only the candidate whose
                                  prefix class meets the range */
+#define HRR_RMQ_DYADIC 4u     /* ablation, not the paper's method: the range split into maximal
+                                 aligned blocks, each block's minimum in closed form */
+#define HRR_RMQ_PAPER_NO_REUSE 5u /* traversal only: HRR_RMQ_PAPER, and the child that holds the
+                                     parent's argmin gets its own query instead of inheriting it
+                                     (ablation of that reuse); hrr_range_min rejects it */
 
 /* For q < n: k = argmin over i in [a[q], b[q]) of (bit_reverse32(i) + r[q])
  * mod 2^32 and v = that minimum (Section 1, v(a,b); Section 2, the argmin

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libhrr.so")
 HRR_OK, HRR_E_INVALID, HRR_E_NOMEM, HRR_E_OVERFLOW = 0, 1, 2, 3
 HRR_E_DEVICE, HRR_E_NOTREADY, HRR_E_CANCELLED, HRR_E_BUSY = 4, 5, 6, 7
 RMQ_PAPER, RMQ_DIRECT, RMQ_PAPER_FULL, RMQ_PAPER_LOOP = 0, 1, 2, 3
+RMQ_DYADIC, RMQ_PAPER_NO_REUSE = 4, 5   # ablations; the second in traversals only
 F_STATS = 1
 F_NO_REORDER = 2
 F_TIMING = 4

@@ -222,7 +222,7 @@ HRR_EXPORT hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint3
                                     uint32_t method, uint32_t* argmin_out, uint32_t* min_out,
                                     unsigned long long* n_invalid_dev, void* stream) {
     if (!ctx) return fail(HRR_E_INVALID, "hrr_range_min: null context");
-    if (method > 3) return fail(HRR_E_INVALID, "hrr_range_min: unknown method %u", method);
+    if (method > 4) return fail(HRR_E_INVALID, "hrr_range_min: unknown method %u", method);
     if (n == 0) return HRR_OK;
     if (!a || !b || !r || !argmin_out || !min_out) return fail(HRR_E_INVALID, "hrr_range_min: null array");
     hipError_t e = hipSetDevice(ctx->device);

@@ -715,6 +715,16 @@ void traverse_kernel(TravArgs A) {
                 }
                 kL = kLeft ? k : kq;
                 kR = kLeft ? kq : k;
+                if (METHOD == 5) {   // ablation: the inheriting child's minimum is recomputed too
+                    const uint32_t ia = kLeft ? a : c, ib = kLeft ? c : b;
+                    uint32_t ki = ia;
+                    if (ib - ia > 1u) {
+                        ki = rmq<METHOD>(ia, ib, E.kr);
+                        if (STATS) ++st_rmq;
+                    }
+                    kL = kLeft ? ki : kL;
+                    kR = kLeft ? kR : ki;
+                }
                 const uint32_t nL = c - a, nR = b - c;
                 const bool leafL = nL <= leaf, leafR = nR <= leaf;
                 const float d2L = box_d2(E.ex, E.ey, E.ez, q0.x, q0.y, q0.z, q1.x, q1.y, q1.z);
@@ -1076,6 +1086,8 @@ extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const
         hipLaunchKernelGGL(hrr::rmq_kernel<2>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     else if (method == 3)
         hipLaunchKernelGGL(hrr::rmq_kernel<3>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
+    else if (method == 4)
+        hipLaunchKernelGGL(hrr::rmq_kernel<4>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     else
         hipLaunchKernelGGL(hrr::rmq_kernel<0>, dim3((uint32_t)blocks), dim3(256), 0, stream, a, b, r, n, k, v, n_bad, vec);
     return hipGetLastError();
@@ -1124,6 +1136,8 @@ hipError_t pick_method(const hrr::TravArgs& A, uint32_t method, bool st, bool w,
     if (method == 1) return pick_stats<EPW, 1>(A, st, w, blocks, lds, s);
     if (method == 2) return pick_stats<EPW, 2>(A, st, w, blocks, lds, s);
     if (method == 3) return pick_stats<EPW, 3>(A, st, w, blocks, lds, s);
+    if (method == 4) return pick_stats<EPW, 4>(A, st, w, blocks, lds, s);
+    if (method == 5) return pick_stats<EPW, 5>(A, st, w, blocks, lds, s);
     return pick_stats<EPW, 0>(A, st, w, blocks, lds, s);
 }
 
@@ -1159,7 +1173,8 @@ extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t me
     if (eyes_per_wave == E && method == M && (stats != 0) == S && (with_weights != 0) == W) \
         f = (const void*)hrr::traverse_kernel<E, M, S, W>;
 #define HRR_PICK_SW(E, M) HRR_PICK(E, M, false, false) HRR_PICK(E, M, false, true) HRR_PICK(E, M, true, false) HRR_PICK(E, M, true, true)
-#define HRR_PICK_M(E) HRR_PICK_SW(E, 0) HRR_PICK_SW(E, 1) HRR_PICK_SW(E, 2) HRR_PICK_SW(E, 3)
+#define HRR_PICK_M(E) \
+    HRR_PICK_SW(E, 0) HRR_PICK_SW(E, 1) HRR_PICK_SW(E, 2) HRR_PICK_SW(E, 3) HRR_PICK_SW(E, 4) HRR_PICK_SW(E, 5)
     HRR_PICK_M(1) HRR_PICK_M(2) HRR_PICK_M(4) HRR_PICK_M(8)
 #undef HRR_PICK_M
 #undef HRR_PICK_SW

@@ -59,7 +59,7 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         return fail(HRR_E_INVALID, "eyes_per_wave must be 1, 2, 4 or 8");
     if (!is_pow2(cap) || cap < 256 || cap > 4096)
         return fail(HRR_E_INVALID, "stack_entries must be a power of two in [256, 4096]");
-    if (method > 3) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
+    if (method > 5) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
     if (n_samples == 0) n_samples = 1;
     const int with_w = weights != nullptr;
 

@@ -296,17 +296,55 @@ HRR_HD uint32_t rmq_paper_select(uint32_t a, uint32_t b, uint32_t kr) {
     return first ? kr : k;
 }
 
+// Not the paper's method (an ablation): the range split into maximal aligned
+// blocks [p, p + 2^s).  Inside one block bitreverse(p + q) = bitreverse(p) +
+// bitreverse_s(q) 2^(32-s), so with u = bitreverse(p) + R the block's values
+// are u + x 2^(32-s) (mod 2^32) over all x < 2^s: the minimum is u mod
+// 2^(32-s), at x = -(u div 2^(32-s)) mod 2^s, i.e. at index p +
+// bitreverse_s(x).  The range minimum is the smallest block minimum (the
+// values are distinct).  R comes back from k_r = bitreverse(-R).
+HRR_HD uint32_t rmq_dyadic(uint32_t a, uint32_t b, uint32_t kr) {
+    const uint32_t R = 0u - bit_reverse(kr);
+    uint32_t best_v = 0, best_k = a;
+    bool found = false;
+    uint32_t p = a;
+    while (p < b) {
+        const int room = top_bit(b - p);                  // largest s with 2^s <= b - p
+        const int s = p ? (bottom_bit(p) < room ? bottom_bit(p) : room) : room;
+        const uint32_t u = bit_reverse(p) + R;
+        uint32_t v = u, k = p;
+        if (s > 0) {
+            const int sh = 32 - s;                        // s <= 31: b < 2^32
+            v = u & low_mask(sh);
+            const uint32_t x = (0u - (u >> sh)) & low_mask(s);
+            k = p + (bit_reverse(x) >> sh);
+        }
+        if (!found || v < best_v) {
+            best_v = v;
+            best_k = k;
+            found = true;
+        }
+        if (b - p <= (1u << s)) break;                    // the last block (no wrap past 2^32 - 1)
+        p += 1u << s;
+    }
+    return best_k;
+}
+
 // METHOD 0: the paper's sweeps, candidate positions selected bit-parallel,
 //           Algorithm 3 refinement (default);
 //        1: closed form of every step (ablation, no refinement walk);
 //        2: the paper's sweeps refining every candidate in turn (ablation);
 //        3: the paper's sweeps as loops, refining only the candidate that
-//           meets the range (ablation).
+//           meets the range (ablation);
+//        4: the dyadic block decomposition (ablation, not the paper's method);
+//        5: the default method; the traversal then also recomputes the minimum
+//           of the child that holds the parent's argmin (ablation of the reuse).
 template <int METHOD>
 HRR_HD uint32_t rmq(uint32_t a, uint32_t b, uint32_t kr) {
     if (METHOD == 1) return rmq_direct(a, b, kr);
     if (METHOD == 2) return rmq_paper(a, b, kr);
     if (METHOD == 3) return rmq_paper_pruned(a, b, kr);
+    if (METHOD == 4) return rmq_dyadic(a, b, kr);
     return rmq_paper_select(a, b, kr);
 }
 

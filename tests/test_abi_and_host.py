@@ -440,7 +440,7 @@ def test_output_compaction_fills_every_position(compact_harness, count, extra, s
 RMQ_HARNESS = r"""
 #include <cstdio>
 #include "hrr_rmq.hpp"
-// stdin: n, then n lines "a b R"; stdout per query: argmin of each method 0..3
+// stdin: n, then n lines "a b R"; stdout per query: argmin of each method 0..4
 int main() {
     unsigned n;
     if (scanf("%u", &n) != 1) return 2;
@@ -448,8 +448,8 @@ int main() {
         unsigned a, b, R;
         if (scanf("%u %u %u", &a, &b, &R) != 3) return 3;
         const unsigned kr = hrr::threshold_index(R);
-        printf("%u %u %u %u\n", hrr::rmq<0>(a, b, kr), hrr::rmq<1>(a, b, kr), hrr::rmq<2>(a, b, kr),
-               hrr::rmq<3>(a, b, kr));
+        printf("%u %u %u %u %u\n", hrr::rmq<0>(a, b, kr), hrr::rmq<1>(a, b, kr), hrr::rmq<2>(a, b, kr),
+               hrr::rmq<3>(a, b, kr), hrr::rmq<4>(a, b, kr));
     }
     return 0;
 }
@@ -506,7 +506,7 @@ def test_device_range_minimum_code_on_the_host(orc, rmq_harness):
     out = subprocess.run([rmq_harness], input=inp, capture_output=True, text=True, check=True).stdout
     got = np.array([[int(x) for x in ln.split()] for ln in out.splitlines()], np.uint64)
     want, _ = orc.rmq_scan(a, b, r)
-    for m in range(4):
+    for m in range(5):
         assert np.array_equal(got[:, m], want.astype(np.uint64)), "method %d" % m
 
 

@@ -11,7 +11,8 @@ import synth
 pytestmark = pytest.mark.gpu
 
 M32 = 0xFFFFFFFF
-METHODS = [0, 1, 2, 3]   # paper (default), closed form, unpruned sweep, pruned loop sweep
+METHODS = [0, 1, 2, 3, 4]   # paper (default), closed form, unpruned sweep, pruned loop sweep,
+                            # aligned blocks
 
 
 @pytest.fixture(scope="module")
@@ -143,3 +144,12 @@ def test_zero_queries(ctx):
     e = torch.empty(0, dtype=torch.int32, device=ctx.torch_device)
     k, v = ctx.range_min(e, e, e)
     assert k.numel() == 0 and v.numel() == 0
+
+
+def test_traversal_only_method_rejected(ctx):
+    import paper_1907_12343_amd as hrr
+    a = np.array([0, 3], np.uint32)
+    with pytest.raises(hrr.HrrError):
+        _run(ctx, a, a + 5, a, hrr.RMQ_PAPER_NO_REUSE)
+    with pytest.raises(hrr.HrrError):
+        _run(ctx, a, a + 5, a, 6)

@@ -52,7 +52,7 @@ def test_light_order_matches_oracle(ctx, orc, tiny, tiny_oracle):
         h.free()
 
 
-@pytest.mark.parametrize("method", [0, 1, 2, 3])
+@pytest.mark.parametrize("method", [0, 1, 2, 3, 4, 5])
 @pytest.mark.parametrize("leaf", [1, 2, 4, 8])
 @pytest.mark.parametrize("epw", [1, 2, 4, 8])
 def test_tiny_full_parity(ctx, tiny, tiny_oracle, method, leaf, epw):
