@@ -266,6 +266,31 @@ def test_keep_decisions_at_the_threshold(ctx, orc):
         h.free()
 
 
+@pytest.mark.parametrize("s", [3.4028235e38, 1e30, 2.0 ** 61, 2.0 ** 60, 2.0 ** -60, 2.0 ** -61, 1e-30,
+                               1.4e-45])
+def test_extreme_s(ctx, orc, tiny, s):
+    """Values of s at and beyond the range of the kernel's product-form test
+    (2^-60 .. 2^60) and up to accepting the whole product set: the decisions
+    then come from the IEEE division alone and must still equal the oracle's.
+    Two eyes sit exactly on a light (d^2 = 0, p = 1)."""
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=1)
+    ls = h.sorted_lights()
+    eyes = np.ascontiguousarray(tiny["eyes"][:512]).copy()
+    eyes[7] = ls[5]
+    eyes[300] = ls[1000]
+    pairs, n, _ = ctx.traverse_all(h, _eyes_t(ctx, eyes), s, tiny["width"])
+    sel = np.arange(eyes.shape[0])
+    out = orc.accept_eyes(eyes, sel, tiny["width"], 0, tiny["tile"], ls, s, lists=True)
+    exp = pair_keys_from_oracle(out, sel)
+    assert n == exp.size
+    assert np.array_equal(pair_keys_from_gpu(pairs), exp)
+    if s >= 1e30:
+        assert n == eyes.shape[0] * ls.shape[0]          # every pair is kept
+    for j, i in ((7, 5), (300, 1000)):                   # a light under the eye is always kept
+        assert (np.uint64(j) << np.uint64(32)) | np.uint64(i) in set(exp.tolist())
+    h.free()
+
+
 def test_coincident_lights_split_at_midpoint(ctx, orc):
     base = synth.uniform_points(40, 950)
     lights = np.repeat(base, 25, axis=0)            # 25 copies each: equal Morton codes
