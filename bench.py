@@ -306,8 +306,9 @@ def _ops_of(st, n_pairs):
 
 def batched_workload(args):
     """256 independent caches (own mixture, 2^U[10,20] lights, 2^U[10,16]
-    eyes, s = 1e-4) in ONE persistent launch, against 256 plain launches of
-    the same items on the same GPU.  The launch shape and the leaf size come
+    eyes, s = 1e-4) in ONE call -- one persistent launch per eyes-per-wave
+    group of the items -- against 256 plain launches of the same items on the
+    same GPU.  The launch shape and the leaf size come
     from the autotuner, run once before timing on the cache with the most
     estimated work (eyes x lights^0.6)."""
     import numpy as np
@@ -380,7 +381,8 @@ def batched_workload(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32",
         "data": "synthetic",
         "config": {"workload": "batched: 256 caches, own 64-Gaussian mixture each, 2^U[10,20] "
-                               "lights, 2^U[10,16] eyes, s=1e-4, one launch",
+                               "lights, 2^U[10,16] eyes, s=1e-4, one call (a launch per "
+                               "eyes-per-wave group)",
                    "n_eyes": n_eyes, "n_lights": int(sizes.sum()), "leaf": leaf,
                    "tuned": tuned, "parallelism": "1 GPU"},
         "pairs_per_s": total / (ms * 1e-3), "accepted_pairs": total, "kernel_ms": gpu_ms,

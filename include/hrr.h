@@ -194,7 +194,7 @@ typedef struct hrr_eyes {
                                call's stream (hrr_stats.kernel_ms) */
 
 typedef struct hrr_traverse_opts {
-    uint32_t eyes_per_wave; /* 0 = autotuned; else 1, 2, 4 or 8 eyes share one wavefront */
+    uint32_t eyes_per_wave; /* 0 = tuned or by hierarchy size; else 1, 2, 4 or 8 eyes share one wavefront */
     uint32_t stack_entries; /* 0 = autotuned; else LDS stack entries per wave, power of two in [256, 4096] */
     uint32_t rmq_method;    /* HRR_RMQ_PAPER (default) or one of the HRR_RMQ_* ablations */
     uint32_t n_samples;     /* 0 or 1 = one sample per pair; > 1: Section 3 multi-sample */
@@ -242,11 +242,17 @@ typedef struct hrr_work_item {
     uint64_t out_capacity;
 } hrr_work_item;
 
-/* Many independent (hierarchy, eye set) items in ONE persistent launch fed by
- * a device work queue.  items: host array.  counts_out (host u64[n_items])
+/* Many independent (hierarchy, eye set) items in one persistent launch fed by
+ * a device work queue.  With opts->eyes_per_wave = 0 each item's shape is
+ * resolved on its own (tuned entry of its light class or a neighbouring one,
+ * else 8 eyes per wave below 2^16 lights, 4 below 2^17, then 1) and the call
+ * enqueues one such launch per group of equal shape on `stream`, largest
+ * hierarchies first.  items: host array.  counts_out (host u64[n_items])
  * receives each item's true pair count; items whose count exceeds their
  * capacity store only the first out_capacity pairs and make the call return
- * HRR_E_OVERFLOW.  Other arguments as hrr_traverse.  Synchronous. */
+ * HRR_E_OVERFLOW.  stats (optional) sums the work of all launches (max_stack:
+ * the largest) and kernel_ms their traversal kernels.  Other arguments as
+ * hrr_traverse.  Synchronous. */
 hrr_status hrr_traverse_batched(hrr_ctx* ctx, const hrr_work_item* items,
                                 uint32_t n_items, const hrr_traverse_opts* opts,
                                 uint32_t* pairs_out, float* weights_out,
@@ -266,8 +272,10 @@ typedef struct hrr_tune_result {
 /* Time candidate launch shapes (eyes per wave x stack entries) for eyes of
  * `eyes` against each hierarchy in hs[0..n_h) -- normally the same lights
  * built with different leaf sizes -- and remember the fastest for hierarchies
- * of this size class and this eye count class.  Later launches with
- * eyes_per_wave = 0 or stack_entries = 0 use the remembered choice.  The
+ * of this size class (log2 of the light count) and this eye count class.
+ * Later launches with eyes_per_wave = 0 or stack_entries = 0 on hierarchies
+ * of the same or a neighbouring size class use the remembered choice (the
+ * nearest entry); other sizes use the built-in rule.  The
  * probe uses at most max_probe_eyes eyes and a scratch output the library
  * allocates.  best (host, optional) receives the winner. */
 hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs, uint32_t n_h,

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "hrr_ctx.hpp"
+#include "hrr_layout.hpp"
 
 #define HRR_EXPORT extern "C" __attribute__((visibility("default")))
 
@@ -111,9 +112,10 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
             const TuneKey key{ilog2_floor(n_lights), ilog2_floor(n_eyes)};
             auto it = ctx->tune.find(key);
             if (it == ctx->tune.end()) {
-                // nearest tuned light class for this eye class, else any
+                // nearest tuned entry of the same or a neighbouring light class
                 int best = 1 << 30;
                 for (auto& kv : ctx->tune) {
+                    if (abs(kv.first.log_lights - key.log_lights) > 1) continue;
                     const int d = abs(kv.first.log_lights - key.log_lights) * 4 + abs(kv.first.log_eyes - key.log_eyes);
                     if (d < best) {
                         best = d;
@@ -126,7 +128,7 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
                 found = true;
             }
         }
-        if (e == 0) e = found ? tv.eyes_per_wave : (n_lights >= (1u << 14) ? 1u : n_lights >= (1u << 11) ? 2u : 4u);
+        if (e == 0) e = found ? tv.eyes_per_wave : default_eyes_per_wave(n_lights);
         if (c == 0) c = found ? tv.stack_entries : 512u;
     }
     *epw = e;
@@ -210,6 +212,7 @@ HRR_EXPORT void hrr_destroy(hrr_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     hrr_server_shutdown(ctx);
     release_scratch(ctx->scratch);
+    for (auto& g : ctx->group_scratch) release_scratch(g);
     if (ctx->d_tile) (void)hipFree(ctx->d_tile);
     delete ctx;
 }
@@ -351,11 +354,17 @@ HRR_EXPORT void hrr_free_hierarchy(hrr_ctx* ctx, hrr_hierarchy* h) {
 // traversal
 // ---------------------------------------------------------------------------
 
+// One synchronous traversal call.  With the shape left to the library
+// (eyes_per_wave = 0, no override) a call of several items groups them by
+// their own shape -- hierarchies of different sizes want different numbers of
+// eyes per wave -- and enqueues one launch per group on `stream` (largest
+// hierarchies first), each with its own scratch; otherwise one launch.
 static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, const hrr_traverse_opts* opts,
                            uint32_t* pairs, float* weights, uint64_t* counts, hrr_stats* stats, hipStream_t stream,
                            uint32_t epw_override = 0, uint32_t cap_override = 0) {
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const size_t n = items.size();
     uint64_t max_eyes = 0;
     uint32_t max_lights = 0;
     for (auto& it : items) {
@@ -366,39 +375,93 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
     resolve_shape(ctx, opts, max_lights, max_eyes, &epw, &cap);
     if (epw_override) epw = epw_override;
     if (cap_override) cap = cap_override;
+
+    // groups of items (indices into `items`) and their eyes per wave
+    constexpr int kMaxGroups = 4;
+    std::vector<size_t> group[kMaxGroups];
+    uint32_t group_epw[kMaxGroups] = {0, 0, 0, 0};
+    int n_groups = 1;
+    const bool per_item = n > 1 && epw_override == 0 && !(opts && opts->eyes_per_wave);
+    if (per_item) {
+        std::vector<uint32_t> item_epw(n, 1u);   // an item without a hierarchy fails in the first launch
+        for (size_t k = 0; k < n; ++k) {
+            uint32_t kc = 0;
+            if (items[k].h) resolve_shape(ctx, opts, items[k].h->n_lights, items[k].eyes.n, &item_epw[k], &kc);
+            const uint32_t ke = item_epw[k];
+            if (!(ke == 1 || ke == 2 || ke == 4 || ke == 8)) item_epw[k] = 1;
+        }
+        n_groups = 0;
+        for (uint32_t ge : {1u, 2u, 4u, 8u}) {
+            std::vector<size_t> g;
+            for (size_t k = 0; k < n; ++k)
+                if (item_epw[k] == ge) g.push_back(k);
+            if (!g.empty()) {
+                group[n_groups] = std::move(g);
+                group_epw[n_groups] = ge;
+                ++n_groups;
+            }
+        }
+    } else {
+        group[0].resize(n);
+        for (size_t k = 0; k < n; ++k) group[0][k] = k;
+        group_epw[0] = epw;
+    }
+    LaunchScratch* scr[kMaxGroups] = {&ctx->scratch, &ctx->group_scratch[0], &ctx->group_scratch[1],
+                                      &ctx->group_scratch[2]};
+
     const uint32_t method = opts ? opts->rmq_method : HRR_RMQ_PAPER;
     const uint32_t ns = opts && opts->n_samples > 1 ? opts->n_samples : 1;
     const uint32_t s0 = opts ? opts->psi_s0 : 0;
     const bool want_stats = opts && (opts->flags & HRR_F_STATS);
-    LaunchScratch& S = ctx->scratch;
     const bool reorder = !(opts && (opts->flags & HRR_F_NO_REORDER));
     const bool timing = opts && (opts->flags & HRR_F_TIMING);
-    hrr_status st =
-        launch_items(ctx, S, items, epw, cap, method, ns, s0, want_stats, reorder, pairs, weights, stream, timing);
-    if (st != HRR_OK) return st;
+    std::vector<HostItem> sub;
+    for (int g = 0; g < n_groups; ++g) {
+        sub.clear();
+        for (size_t k : group[g]) sub.push_back(items[k]);
+        const hrr_status st = launch_items(ctx, *scr[g], sub, group_epw[g], cap, method, ns, s0, want_stats, reorder,
+                                           pairs, weights, stream, timing);
+        if (st != HRR_OK) {
+            // launches of earlier groups may be running: let them end before
+            // the caller regains its buffers
+            if (g > 0) (void)hipStreamSynchronize(stream);
+            return st;
+        }
+    }
     if ((e = hipStreamSynchronize(stream)) != hipSuccess) return hip_fail(e, "traverse");
-    if ((st = finish_items(ctx, S)) != HRR_OK) return st;
-    const size_t n = items.size();
+
     bool overflow = false;
     uint64_t total = 0;
-    for (size_t k = 0; k < n; ++k) {
-        counts[k] = S.counts[k];
-        total += counts[k];
-        if (counts[k] > items[k].out_capacity) overflow = true;
+    uint32_t error = 0;
+    unsigned long long agg[ST_N] = {};
+    double kernel_ms = 0.0;
+    for (int g = 0; g < n_groups; ++g) {
+        LaunchScratch& S = *scr[g];
+        hrr_status st = finish_items(ctx, S);
+        if (st != HRR_OK) return st;
+        for (size_t q = 0; q < group[g].size(); ++q) {
+            const size_t k = group[g][q];
+            counts[k] = S.counts[q];
+            total += counts[k];
+            if (counts[k] > items[k].out_capacity) overflow = true;
+        }
+        error |= S.error;
+        for (int q = 0; q < ST_N; ++q) agg[q] = q == ST_MAXSTACK ? std::max(agg[q], S.stat[q]) : agg[q] + S.stat[q];
+        if (timing) kernel_ms += timed_kernel_ms(S);
     }
     if (stats) {
         memset(stats, 0, sizeof *stats);
-        if (want_stats) fill_stats(S.stat, stats);
+        if (want_stats) fill_stats(agg, stats);
         stats->pairs = total;
-        stats->kernel_ms = timing ? timed_kernel_ms(S) : 0.0;
+        stats->kernel_ms = kernel_ms;
     }
-    if (S.error & ERR_SPILL_OVERFLOW)
+    if (error & ERR_SPILL_OVERFLOW)
         return fail(HRR_E_DEVICE, "traversal kernel exhausted its stack spill region");
-    if (S.error & ERR_PARTIALS_OVERFLOW)
+    if (error & ERR_PARTIALS_OVERFLOW)
         return fail(HRR_E_DEVICE, "traversal kernel exhausted its partial-chunk list");
-    if (S.error & ERR_UNFILLED)
+    if (error & ERR_UNFILLED)
         return fail(HRR_E_DEVICE, "output compaction left positions below the count unfilled");
-    if (S.error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", S.error);
+    if (error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", error);
     if (overflow) return fail(HRR_E_OVERFLOW, "output capacity exceeded");
     return HRR_OK;
 }

@@ -97,6 +97,7 @@ struct hrr_ctx {
     uint32_t* d_tile = nullptr;
     uint32_t tile_tz = 32, tile_bits = 0;   // shared trailing zeros / significant bits of the tile values
     hrr::LaunchScratch scratch;   // scratch of the synchronous entry points
+    hrr::LaunchScratch group_scratch[3];   // further launches of one batched call (items grouped by shape)
     std::mutex tune_mu;
     std::map<hrr::TuneKey, hrr::TuneVal> tune;
     std::map<int, uint32_t> tune_leaf;   // log2 lights -> leaf size
@@ -112,8 +113,9 @@ hrr_status hip_fail(hipError_t e, const char* what);
 
 int ilog2_floor(uint64_t x);
 
-// Resolve launch parameters (eyes per wave, stack entries) from options and
-// the tuner.
+// Resolve launch parameters (eyes per wave, stack entries) from options, the
+// tuner (an entry of the same or a neighbouring light class) and the built-in
+// rule default_eyes_per_wave().
 void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes,
                    uint32_t* epw, uint32_t* cap);
 

@@ -55,6 +55,19 @@ inline uint64_t departures_per_wave(uint64_t n, uint32_t interleave_shift) {
     return interleave_shift ? kQueues : (n > 1 ? 2 : 1);
 }
 
+// Eyes per wavefront for a hierarchy of n_lights lights when neither the
+// caller nor the tuner fixes it.  Small hierarchies give an eye only tens to
+// hundreds of node visits, too few to keep 64 lanes busy (one eye per wave:
+// 13 % of the lanes active at 2^10..2^12 lights, 37 % at 2^14..2^16, 89 % at
+// 2^18..2^20), so several eyes share a wave.  Thresholds measured on batched
+// launches of mixture caches at s = 1e-4 (kernel ms at 1 / 4 / 8 eyes per wave:
+// 2^10..2^12 lights 3.82 / 1.40 / 0.76, 2^14..2^16 6.34 / 3.37 / 3.11,
+// 2^16..2^17 3.36 / 3.04 / 3.08, 2^17..2^18 8.90 / 8.94 / 9.08, 2^18..2^20
+// 40.4 / 45.2 / 51.3).
+inline uint32_t default_eyes_per_wave(uint32_t n_lights) {
+    return n_lights >= (1u << 17) ? 1u : n_lights >= (1u << 16) ? 4u : 8u;
+}
+
 // Output chunk size of an item: about sixteen chunks per wave that touches
 // the item, 2^kMinChunkShift .. 2^kMaxChunkShift pairs.
 inline uint32_t chunk_shift_for(uint64_t capacity, uint64_t touching_waves) {

@@ -513,7 +513,7 @@ def test_device_range_minimum_code_on_the_host(orc, rmq_harness):
 LAYOUT_HARNESS = r"""
 #include <cstdio>
 #include "hrr_layout.hpp"
-// stdin lines: "o n virtual_eyes tile_bits" | "q n tasks" | "c capacity waves"
+// stdin lines: "o n virtual_eyes tile_bits" | "q n tasks" | "c capacity waves" | "e n_lights"
 int main() {
     char op;
     unsigned long long a, b, c;
@@ -527,6 +527,8 @@ int main() {
             printf("%u %llu\n", s, (unsigned long long)hrr::departures_per_wave(a, s));
         } else if (op == 'c' && scanf("%llu %llu", &a, &b) == 2) {
             printf("%u\n", hrr::chunk_shift_for(a, b));
+        } else if (op == 'e' && scanf("%llu", &a) == 1) {
+            printf("%u\n", hrr::default_eyes_per_wave((uint32_t)a));
         } else {
             return 1;
         }
@@ -553,8 +555,9 @@ def _ask(exe, lines):
 
 
 def test_launch_layout_choices(layout_harness):
-    """Eye-order key widths, queue layout, departures per wave and chunk size
-    of a launch, for the benchmark shapes and the boundaries of each rule."""
+    """Eye-order key widths, queue layout, departures per wave, chunk size and
+    default eyes per wave of a launch, for the benchmark shapes and the
+    boundaries of each rule."""
     ask = lambda lines: _ask(layout_harness, lines)
     # order key: frame (3 bits per axis, 9 class bits), 256 caches (2, 6), a
     # small item (2, 9), the bucket budget, tiles without class bits
@@ -581,3 +584,6 @@ def test_launch_layout_choices(layout_harness):
     w = 7168
     assert ask(["c 0 1", "c %d 1" % (1 << 40), "c 4829514196 %d" % w, "c %d %d" % (16 * w * 256, w),
                 "c %d %d" % (16 * w * 256 - 1, w)]) == [(7,), (13,), (13,), (8,), (7,)]
+    # eyes per wave by hierarchy size: 8 below 2^16 lights, 4 below 2^17, then 1
+    assert ask(["e 0", "e 1024", "e 65535", "e 65536", "e 131071", "e 131072", "e 1048576",
+                "e 4294967295"]) == [(8,), (8,), (8,), (4,), (4,), (1,), (1,), (1,)]

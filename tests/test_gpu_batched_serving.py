@@ -91,6 +91,62 @@ def test_batched_items_equal_plain_and_oracle(ctx, orc):
         h.free()
 
 
+def test_batched_groups_by_hierarchy_size(ctx, hrr):
+    """Items whose hierarchies want different eyes per wave (8 below 2^16
+    lights, 4 below 2^17, else 1) run as one launch per group; every item
+    equals a plain one-eye-per-wave launch pair for pair and weight for
+    weight, work statistics add up exactly, and an overflow stays per item."""
+    import torch
+    sizes = [1 << 11, (1 << 17) + 5, 1 << 16, 1 << 12, 1 << 18, 1 << 11]
+    caches = []
+    for c, nl in enumerate(sizes):
+        d = synth.batched_cache(20 + c)
+        lights = d["lights"]
+        if lights.shape[0] < nl:
+            lights = synth.mixture_points(nl, np.random.default_rng(900 + c).random((64, 3)), 910 + c)
+        caches.append(dict(lights=np.ascontiguousarray(lights[:nl]), eyes=d["eyes"][:1 << 12],
+                           width=d["width"], s=d["s"]))
+    hs = [ctx.build_hierarchy(d["lights"]) for d in caches]
+    eyes = [_dev(ctx, d["eyes"]) for d in caches]
+    plain = [ctx.traverse_all(h, e, d["s"], d["width"], eyes_per_wave=1, stack_entries=512,
+                              with_weights=True, stats=True)
+             for h, e, d in zip(hs, eyes, caches)]
+    counts = [p[1] for p in plain]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    pairs = torch.empty((int(offs[-1]), 2), dtype=torch.int32, device=ctx.torch_device)
+    weights = torch.empty((int(offs[-1]),), dtype=torch.float32, device=ctx.torch_device)
+    items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=int(offs[k]),
+                  out_capacity=int(counts[k]))
+             for k, (h, e, d) in enumerate(zip(hs, eyes, caches))]
+    got, st = ctx.traverse_batched(items, pairs, weights=weights, stats=True, timing=True)
+    assert [int(x) for x in got] == counts
+    for k in range(len(caches)):
+        sl = slice(int(offs[k]), int(offs[k + 1]))
+        assert _pairs_with_weights(pairs[sl], weights[sl]) == \
+            _pairs_with_weights(plain[k][0], plain[k][3]), k
+    for key in ("node_visits", "rmq_calls", "leaf_tests", "eyes"):
+        assert st[key] == sum(p[2][key] for p in plain), key
+    assert st["pairs"] == sum(counts) and st["kernel_ms"] > 0
+    # one item of the 8-eye group over its capacity: the others stay complete
+    caps = list(counts)
+    caps[3] = counts[3] // 2
+    offs2 = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
+    items2 = [dict(it, out_offset=int(offs2[k]), out_capacity=int(caps[k])) for k, it in enumerate(items)]
+    pairs.fill_(-1)
+    with pytest.raises(hrr.OverflowResult) as ei:
+        ctx.traverse_batched(items2, pairs)
+    assert [int(x) for x in ei.value.counts] == counts
+    for k in range(len(caches)):
+        keys = pair_keys_from_gpu(pairs[int(offs2[k]):int(offs2[k + 1])])
+        full = pair_keys_from_gpu(plain[k][0])
+        if k == 3:
+            assert keys.size == caps[3] and np.unique(keys).size == keys.size and np.isin(keys, full).all()
+        else:
+            assert np.array_equal(keys, full), k
+    for h in hs:
+        h.free()
+
+
 def test_batched_overflow_is_per_item(ctx, hrr):
     import torch
     caches = [_small_cache(c, 1 << 12, 1 << 10) for c in range(3)]
