@@ -188,8 +188,22 @@ __device__ __forceinline__ void rmq_one(uint32_t a, uint32_t b, uint32_t R, uint
 
 // Four queries per lane per step through 16-byte loads when every array is
 // 16-byte aligned (vec != 0); the scalar tail and unaligned arrays go one
-// query at a time.
+// query at a time.  Every array is touched once, so loads and stores are
+// non-temporal (2^28 queries: 0.895 ms against 0.970 ms with ordinary ones;
+// non-temporal stores alone 0.96 ms, loads alone 0.98 ms).
 constexpr uint32_t kRmqGroups = 2;   // 4-query groups per thread (2: 0.98 ms, 1: 1.02 ms, 4: 1.00 ms for 2^28)
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint4 load_stream4(const uint4* p, uint64_t i) {
+    const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p) + i);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void store_stream4(uint4* p, uint64_t i, uint4 x) {
+    const u32x4 v = {x.x, x.y, x.z, x.w};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x4*>(p) + i);
+}
 
 template <int METHOD>
 __global__ __launch_bounds__(256) void rmq_kernel(const uint32_t* __restrict__ A, const uint32_t* __restrict__ B,
@@ -217,9 +231,9 @@ __global__ __launch_bounds__(256) void rmq_kernel(const uint32_t* __restrict__ A
             for (uint32_t g = 0; g < kRmqGroups; ++g) {
                 const uint64_t q = base + g * blockDim.x + threadIdx.x;
                 if (q < n4) {
-                    a[g] = A4[q];
-                    b[g] = B4[q];
-                    r[g] = R4[q];
+                    a[g] = load_stream4(A4, q);
+                    b[g] = load_stream4(B4, q);
+                    r[g] = load_stream4(R4, q);
                 }
             }
 #pragma unroll
@@ -231,8 +245,8 @@ __global__ __launch_bounds__(256) void rmq_kernel(const uint32_t* __restrict__ A
                     rmq_one<METHOD>(a[g].y, b[g].y, r[g].y, k.y, v.y, bad);
                     rmq_one<METHOD>(a[g].z, b[g].z, r[g].z, k.z, v.z, bad);
                     rmq_one<METHOD>(a[g].w, b[g].w, r[g].w, k.w, v.w, bad);
-                    K4[q] = k;
-                    V4[q] = v;
+                    store_stream4(K4, q, k);
+                    store_stream4(V4, q, v);
                 }
             }
         }
@@ -240,9 +254,10 @@ __global__ __launch_bounds__(256) void rmq_kernel(const uint32_t* __restrict__ A
     }
     for (uint64_t q = done + tid; q < n; q += stride) {
         uint32_t k, v;
-        rmq_one<METHOD>(A[q], B[q], R[q], k, v, bad);
-        K[q] = k;
-        V[q] = v;
+        rmq_one<METHOD>(__builtin_nontemporal_load(A + q), __builtin_nontemporal_load(B + q),
+                        __builtin_nontemporal_load(R + q), k, v, bad);
+        __builtin_nontemporal_store(k, K + q);
+        __builtin_nontemporal_store(v, V + q);
     }
     if (n_bad) {
         const uint64_t m = ballot(bad != 0);
