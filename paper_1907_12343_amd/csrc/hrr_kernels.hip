@@ -372,6 +372,20 @@ __device__ __forceinline__ unsigned long long alloc_chunk(const ItemDesc& D) {
     return uni64(c);
 }
 
+// Pairs and weights are written once and not read again by the launch:
+// non-temporal stores keep them from displacing node records in the caches
+// (frame 144.5 -> 141.9 ms, 256-cache batch 57.2 -> 55.8 ms).
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void put_pair(uint2* p, unsigned long long i, uint2 x) {
+    const u32x2 v = {x.x, x.y};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(p) + i);
+}
+
+__device__ __forceinline__ void put_weight(float* p, unsigned long long i, float w) {
+    __builtin_nontemporal_store(w, p + i);
+}
+
 // Make `c` the current chunk; direct pointers when the whole chunk lies below
 // the capacity or inside the slack area (a chunk that straddles the capacity
 // or the end of the slack takes the per-pair path).
@@ -395,12 +409,12 @@ __device__ __forceinline__ void set_chunk(OutState& O, const ItemDesc& D, unsign
 template <bool W>
 __device__ __forceinline__ void store_pair(const ItemDesc& D, unsigned long long p, uint2 pr, float w) {
     if (p < D.capacity) {
-        reinterpret_cast<uint2*>(D.pairs)[p] = pr;
-        if (W) D.weights[p] = w;
+        put_pair(reinterpret_cast<uint2*>(D.pairs), p, pr);
+        if (W) put_weight(D.weights, p, w);
     } else if (p - D.capacity < D.slack) {
         const unsigned long long q = p - D.capacity;
-        reinterpret_cast<uint2*>(D.slack_pairs)[q] = pr;
-        if (W) D.slack_weights[q] = w;
+        put_pair(reinterpret_cast<uint2*>(D.slack_pairs), q, pr);
+        if (W) put_weight(D.slack_weights, q, w);
     }
 }
 
@@ -427,12 +441,12 @@ __device__ __forceinline__ void emit2(OutState& O, const ItemDesc& D, bool e0, u
     const uint32_t pos1 = pos0 + (e0 ? 1u : 0u);
     if (O.wp && O.fill + cnt <= C) {
         if (e0) {
-            O.wp[pos0] = p0;
-            if (W) O.ww[pos0] = w0;
+            put_pair(O.wp, pos0, p0);
+            if (W) put_weight(O.ww, pos0, w0);
         }
         if (e1) {
-            O.wp[pos1] = p1;
-            if (W) O.ww[pos1] = w1;
+            put_pair(O.wp, pos1, p1);
+            if (W) put_weight(O.ww, pos1, w1);
         }
         O.fill += cnt;
         O.count += cnt;
