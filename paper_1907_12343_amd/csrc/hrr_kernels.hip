@@ -191,7 +191,7 @@ __device__ __forceinline__ void rmq_one(uint32_t a, uint32_t b, uint32_t R, uint
 // query at a time.  Every array is touched once, so loads and stores are
 // non-temporal (2^28 queries: 0.895 ms against 0.970 ms with ordinary ones;
 // non-temporal stores alone 0.96 ms, loads alone 0.98 ms).
-constexpr uint32_t kRmqGroups = 2;   // 4-query groups per thread (2: 0.98 ms, 1: 1.02 ms, 4: 1.00 ms for 2^28)
+constexpr uint32_t kRmqGroups = 1;   // 4-query groups per thread (2^28 queries: 1: 0.925 ms, 2: 0.941, 4: 0.955)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -680,6 +680,9 @@ void traverse_kernel(TravArgs A) {
         // -------- top-down walk --------
         while (S.n + S.g > 0) {
             if (S.n < kWave && S.g > 0) stack_refill(S, L, spill, cap);
+            // the wave issues its record loads at raised priority, so that
+            // they leave early (frame 142.9 -> 142.1 ms)
+            __builtin_amdgcn_s_setprio(1);
             const uint32_t n = min(S.n, (uint32_t)kWave);
             const uint32_t top = S.g + S.n;
             const bool act = lane < n;
@@ -719,6 +722,7 @@ void traverse_kernel(TravArgs A) {
                 float4 e02 = make_float4(0.f, 0.f, 0.f, 0.f), e13 = e02, o02 = e02, o13 = e02;
                 if ((lane & ~1u) < n) { e02 = load_global4(re, h); e13 = load_global4(re, 2u + h); }
                 if ((lane | 1u) < n) { o02 = load_global4(ro, h); o13 = load_global4(ro, 2u + h); }
+                __builtin_amdgcn_s_setprio(0);
                 // even lane holds chunks 0, 2 of both records, odd lane chunks 1, 3
                 const float4 r1 = swap_pairs(odd ? e02 : o02);
                 const float4 r2 = swap_pairs(odd ? e13 : o13);
@@ -1100,9 +1104,10 @@ extern "C" hipError_t hrr_launch_rmq(const uint32_t* a, const uint32_t* b, const
     const int vec = ((((uintptr_t)a) | ((uintptr_t)b) | ((uintptr_t)r) | ((uintptr_t)k) | ((uintptr_t)v)) & 15u) == 0;
     const uint64_t work = vec ? (n + 3) / 4 : n;
     // kRmqGroups 4-query groups per thread and a grid far larger than the
-    // resident capacity keep the most loads in flight (2^28 queries: 1.26 ms
-    // with 16 blocks per CU and a grid-stride loop, 1.02 ms with one group
-    // per thread, 0.98 ms with two).  The loop still covers grids above the cap.
+    // resident capacity keep the most loads in flight (2^28 queries with
+    // ordinary loads: 1.26 ms with 16 blocks per CU and a grid-stride loop,
+    // 1.02 ms with one group per thread, 0.98 ms with two; with non-temporal
+    // loads one group is best).  The loop still covers grids above the cap.
     const uint64_t per_block = vec ? 256ull * hrr::kRmqGroups : 256ull;
     uint64_t blocks = (work + per_block - 1) / per_block;
     const uint64_t max_blocks = 1ull << 30;
