@@ -542,7 +542,9 @@ def main():
                    help="served: seconds of arrivals per offered load")
     p.add_argument("--rmq", default="paper", choices=list(RMQ_METHODS),
                    help="range-minimum method: paper (bit-parallel flip-position selection, "
-                        "default), direct, paper_full (sweeps as loops), paper_loop (pruned loops)")
+                        "default), direct, paper_full (sweeps as loops), paper_loop (pruned loops), "
+                        "dyadic (aligned blocks, not the paper's), paper_no_reuse (frame only: "
+                        "no inheritance of the parent's argmin)")
     p.add_argument("--samples", type=int, default=1,
                    help="frame: samples per eye (rotation psi(n) per sample; fewer pixel rows)")
     p.add_argument("--weights", action="store_true", help="frame: also write 1/p per pair")
