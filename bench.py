@@ -548,7 +548,9 @@ def main():
     p.add_argument("--samples", type=int, default=1,
                    help="frame: samples per eye (rotation psi(n) per sample; fewer pixel rows)")
     p.add_argument("--weights", action="store_true", help="frame: also write 1/p per pair")
-    p.add_argument("--epw", type=int, default=1)
+    p.add_argument("--epw", type=int, default=0,
+                   help="eyes per wave: 0 = the library's choice by hierarchy size (1 for the "
+                        "frame's 2^20 lights, 8 for the small case), else 1, 2, 4 or 8")
     p.add_argument("--stack", type=int, default=512)
     p.add_argument("--traffic-kib", type=float, nargs=2, default=None,
                    metavar=("FETCH", "WRITE"),
