@@ -269,6 +269,40 @@ def test_batched_256_caches_counts_match_plain(ctx):
         h.free()
 
 
+def test_batched_256_caches_sampled_parity(ctx, orc):
+    """The 256-cache workload at its real sizes in the benchmark's launch
+    configuration (shape left to the library: one launch per eyes-per-wave
+    group, leaf 1), all 1.35e9 pairs stored: counts equal plain counts, and
+    sampled eyes of items from every group equal the oracle pair for pair."""
+    import torch
+    caches = [synth.batched_cache(c) for c in range(256)]
+    hs = [ctx.build_hierarchy(d["lights"]) for d in caches]
+    eyes = [_dev(ctx, d["eyes"]) for d in caches]
+    counts = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
+    offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    pairs = torch.empty((int(offs[-1]), 2), dtype=torch.int32, device=ctx.torch_device)
+    items = [dict(h=h, eyes=e, s=d["s"], width=d["width"], out_offset=int(offs[k]),
+                  out_capacity=int(counts[k]))
+             for k, (h, e, d) in enumerate(zip(hs, eyes, caches))]
+    got, _ = ctx.traverse_batched(items, pairs)
+    assert [int(x) for x in got] == counts
+    sizes = np.array([d["lights"].shape[0] for d in caches])
+    order = np.argsort(sizes, kind="stable")
+    band = lambda lo, hi: [int(k) for k in order if lo <= sizes[k] < hi][:2]
+    pick = [int(k) for k in order[:2]] + band(1 << 13, 1 << 16) + band(1 << 16, 1 << 17) + \
+        band(1 << 17, 1 << 18) + [int(k) for k in order[-2:]]
+    rng = np.random.default_rng(11)
+    for k in pick:
+        d = caches[k]
+        sl = pairs[int(offs[k]):int(offs[k + 1])]
+        sel = np.sort(rng.choice(d["eyes"].shape[0], 6, replace=False)).astype(np.uint32)
+        want = _oracle_keys(orc, d["lights"], d["eyes"], sel, d["width"], 0, d["s"])
+        assert np.array_equal(select_pairs_of_eyes(sl, sel), want), (k, sizes[k])
+    del pairs
+    for h in hs:
+        h.free()
+
+
 # ---------------------------------------------------------------------------
 # autotuner
 # ---------------------------------------------------------------------------
