@@ -72,14 +72,14 @@ def frame_workload(args):
         fr = dict(fr, eyes=np.ascontiguousarray(fr["eyes"][:rows * fr["width"]]))
     ctx = hrr.Context(fr["tile"], device=0)
     t0 = time.time()
-    h = ctx.build_hierarchy(fr["lights"], leaf_size=fr["leaf"])
+    h = ctx.build_hierarchy(fr["lights"], leaf_size=fr["leaf"], split=args.split)
     build_s = time.time() - t0
     lights_dev = torch.from_numpy(fr["lights"]).to("cuda:0")
-    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"])   # warm-up (allocations, code load)
+    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"], split=args.split)   # warm-up
     hd.free()
     _sync_all()
     t0 = time.perf_counter()
-    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"])
+    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"], split=args.split)
     build_dev_s = time.perf_counter() - t0
     hd.free()
     eyes = torch.from_numpy(fr["eyes"]).to("cuda:0")
@@ -131,8 +131,8 @@ def frame_workload(args):
         "vs_baseline": None,
         "dtype": "u32+f32",
         "data": "synthetic",
-        "config": {"workload": _frame_name(ns, args.weights, tiny),
-                   "n_eyes": n_eyes, "n_lights": int(fr["lights"].shape[0]),
+        "config": {"workload": _frame_name(ns, args.weights, tiny, args.split),
+                   "n_eyes": n_eyes, "n_lights": int(fr["lights"].shape[0]), "split": args.split,
                    "rmq": args.rmq, "parallelism": "1 GPU"},
         "pairs_per_s": n / (ms * 1e-3),
         "accepted_pairs": n,
@@ -145,7 +145,8 @@ def frame_workload(args):
         "algorithmic_lane_ops": ops,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": _traffic_bytes(args) if (ns == 1 and not args.weights and not tiny) else None},
+                     "traffic": _traffic_bytes(args, split=args.split)
+                     if (ns == 1 and not args.weights and not tiny) else None},
     }
     if ns > 1:
         line["config"]["samples_per_eye"] = ns
@@ -185,7 +186,7 @@ def kernel_source_digest():
     return h.hexdigest()
 
 
-def _traffic_bytes(args, path=TRAFFIC_FILE):
+def _traffic_bytes(args, path=TRAFFIC_FILE, split=None):
     """HBM bytes of one timed launch of the dominant kernel: FETCH_SIZE +
     WRITE_SIZE from rocprofv3 --pmc runs, scaled by the copy-kernel
     calibration, as recorded in profiles/ together with the digest of the
@@ -200,10 +201,12 @@ def _traffic_bytes(args, path=TRAFFIC_FILE):
         return None
     if rec.get("kernel_sources_sha256") != kernel_source_digest():
         return None
+    if split is not None and rec.get("split", "radix") != split:
+        return None   # counters taken on the other hierarchy
     return (rec["fetch_kib_scaled"] + rec["write_kib_scaled"]) * 1024.0
 
 
-def _frame_name(ns, weights, tiny=False):
+def _frame_name(ns, weights, tiny=False, split="radix"):
     name = "frame: 1920x1080 eyes x 2^20 lights, 64-Gaussian mixture sigma 0.02, s=1e-4, leaf 1"
     if tiny:
         # the small parity case: launch-latency bound, reported for completeness
@@ -211,6 +214,8 @@ def _frame_name(ns, weights, tiny=False):
     elif ns > 1:
         name = ("frame rows 0..%d (1920x%d eyes) x %d samples per eye x 2^20 lights, "
                 "64-Gaussian mixture sigma 0.02, s=1e-4, leaf 1" % (1080 // ns - 1, 1080 // ns, ns))
+    if split == "pow2":
+        name += ", power-of-two splits"
     if weights:
         name += ", 1/p weights"
     return name + ", one launch"
@@ -322,13 +327,13 @@ def batched_workload(args):
     work = np.array([d["eyes"].shape[0] * d["lights"].shape[0] ** 0.6 for d in caches])
     probe = caches[int(np.argmax(work))]   # tune on the cache that dominates the launch
     t0 = time.time()
-    cand = [ctx.build_hierarchy(probe["lights"], leaf_size=L) for L in (1, 2, 4, 8)]
+    cand = [ctx.build_hierarchy(probe["lights"], leaf_size=L, split=args.split) for L in (1, 2, 4, 8)]
     pe = torch.from_numpy(probe["eyes"]).to("cuda:0")
     tuned = ctx.autotune(cand, pe, probe["s"], probe["width"], max_probe_eyes=32768)
     for h in cand:
         h.free()
     leaf = tuned["leaf_size"]
-    hs = [ctx.build_hierarchy(d["lights"], leaf_size=leaf) for d in caches]
+    hs = [ctx.build_hierarchy(d["lights"], leaf_size=leaf, split=args.split) for d in caches]
     setup_s = time.time() - t0
     eyes = [torch.from_numpy(d["eyes"]).to("cuda:0") for d in caches]
     counts = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
@@ -383,7 +388,7 @@ def batched_workload(args):
         "config": {"workload": "batched: 256 caches, own 64-Gaussian mixture each, 2^U[10,20] "
                                "lights, 2^U[10,16] eyes, s=1e-4, one call (a launch per "
                                "eyes-per-wave group)",
-                   "n_eyes": n_eyes, "n_lights": int(sizes.sum()), "leaf": leaf,
+                   "n_eyes": n_eyes, "n_lights": int(sizes.sum()), "leaf": leaf, "split": args.split,
                    "tuned": tuned, "parallelism": "1 GPU"},
         "pairs_per_s": total / (ms * 1e-3), "accepted_pairs": total, "kernel_ms": gpu_ms,
         "step_gpu_ms": step_gpu_ms, "setup_s": setup_s,
@@ -416,7 +421,7 @@ def served_workload(args):
     ctx = hrr.Context(synth.dither_tile(100), device=0)
     t0 = time.time()
     scenes = [synth.served_hierarchy(k) for k in range(16)]
-    hs = [ctx.build_hierarchy(sc["lights"]) for sc in scenes]
+    hs = [ctx.build_hierarchy(sc["lights"], split=args.split) for sc in scenes]
     n_req = args.requests
     base = synth.served_requests(n_req, 1.0)
     req_eyes = [synth.request_eyes(scenes[int(base["hier"][q])]["centers"], int(base["size"][q]),
@@ -545,6 +550,10 @@ def main():
                         "default), direct, paper_full (sweeps as loops), paper_loop (pruned loops), "
                         "dyadic (aligned blocks, not the paper's), paper_no_reuse (frame only: "
                         "no inheritance of the parent's argmin)")
+    p.add_argument("--split", default="pow2", choices=["radix", "pow2"],
+                   help="hierarchy split rule: pow2 (left child = largest power of two below "
+                        "the length; default, 8 %% faster on the frame) or radix (highest "
+                        "differing Morton bit, the library's default)")
     p.add_argument("--samples", type=int, default=1,
                    help="frame: samples per eye (rotation psi(n) per sample; fewer pixel rows)")
     p.add_argument("--weights", action="store_true", help="frame: also write 1/p per pair")

@@ -129,7 +129,15 @@ typedef struct hrr_hierarchy_info {
     uint32_t depth;         /* deepest internal node (root = 0) */
     uint64_t device_bytes;  /* nodes + sorted lights + permutation */
     float box[6];           /* root bounding box lo xyz, hi xyz */
+    uint32_t split;         /* HRR_SPLIT_RADIX or HRR_SPLIT_POW2 */
 } hrr_hierarchy_info;
+
+/* Split rules of a hierarchy build, OR-ed into its leaf_size argument. */
+#define HRR_SPLIT_RADIX 0x000u /* default: at the first index whose Morton code has the highest
+                                  bit in which code[a] and code[b-1] differ (midpoint if equal) */
+#define HRR_SPLIT_POW2 0x100u  /* after the largest power of two below the node's length b - a:
+                                  every left child is an aligned block of 2^k indices, and for a
+                                  power-of-two light count every node is one */
 
 /* Build a binary light hierarchy (Section 1: lights sorted by a hierarchy,
  * each node a contiguous range of sequence indices).  lights_xyz: host,
@@ -137,16 +145,17 @@ typedef struct hrr_hierarchy_info {
  * index); the Morton code interleaves 21-bit cell indices of x, y, z
  * (x highest) against `box` (host, 6 floats lo xyz hi xyz; NULL = unit cube;
  * coordinates outside are clamped for ordering only).  A node [a,b) with
- * b - a > leaf_size is split at the first index whose code has the highest
- * bit in which code[a] and code[b-1] differ (midpoint if they are equal).
- * leaf_size in [1, 8].  Non-finite coordinates return HRR_E_INVALID.
+ * b - a > leaf is split by the rule in leaf_size's flag bits (HRR_SPLIT_*).
+ * leaf_size: the leaf size in [1, 8], optionally OR HRR_SPLIT_POW2; other
+ * bits return HRR_E_INVALID.  Non-finite coordinates return HRR_E_INVALID.
+ * The accepted pairs of a traversal do not depend on the split rule.
  * The hierarchy lives on the context's device until hrr_free_hierarchy. */
 hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz,
                                uint32_t n_lights, uint32_t leaf_size,
                                const float* box, hrr_hierarchy** out);
 /* The same hierarchy built on the GPU (the step before the path, for light
  * caches that already live in device memory): lights_xyz_dev is device
- * memory, 3*n_lights fp32; box and leaf_size as above.  The result is the
+ * memory, 3*n_lights fp32; box and leaf_size (with its split flag) as above.  The result is the
  * one hrr_build_hierarchy returns for the same lights, record for record
  * (same order, splits, exact boxes and preorder numbering): Morton codes,
  * a stable radix sort, one launch per tree level for the splits, then a
@@ -275,7 +284,10 @@ typedef struct hrr_tune_result {
  * of this size class (log2 of the light count) and this eye count class.
  * Later launches with eyes_per_wave = 0 or stack_entries = 0 on hierarchies
  * of the same or a neighbouring size class use the remembered choice (the
- * nearest entry); other sizes use the built-in rule.  The
+ * nearest entry); other sizes use the built-in rule.  Candidates are tried
+ * in order of preference (fewer eyes per wave first; 512 stack entries, then
+ * 256, then 1024) and a later one replaces the best only when it is more than
+ * 2 % faster.  The
  * probe uses at most max_probe_eyes eyes and a scratch output the library
  * allocates.  best (host, optional) receives the winner. */
 hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs, uint32_t n_h,

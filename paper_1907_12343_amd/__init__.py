@@ -23,6 +23,8 @@ HRR_OK, HRR_E_INVALID, HRR_E_NOMEM, HRR_E_OVERFLOW = 0, 1, 2, 3
 HRR_E_DEVICE, HRR_E_NOTREADY, HRR_E_CANCELLED, HRR_E_BUSY = 4, 5, 6, 7
 RMQ_PAPER, RMQ_DIRECT, RMQ_PAPER_FULL, RMQ_PAPER_LOOP = 0, 1, 2, 3
 RMQ_DYADIC, RMQ_PAPER_NO_REUSE = 4, 5   # ablations; the second in traversals only
+SPLIT_RADIX, SPLIT_POW2 = 0x000, 0x100   # hierarchy split rules, OR-ed into leaf_size
+_SPLITS = {"radix": SPLIT_RADIX, "pow2": SPLIT_POW2}
 F_STATS = 1
 F_NO_REORDER = 2
 F_TIMING = 4
@@ -53,7 +55,7 @@ class HrrStats(ctypes.Structure):
 
 class HrrHierarchyInfo(ctypes.Structure):
     _fields_ = [("n_lights", _u32), ("leaf_size", _u32), ("n_nodes", _u32), ("depth", _u32),
-                ("device_bytes", _u64), ("box", _f32 * 6)]
+                ("device_bytes", _u64), ("box", _f32 * 6), ("split", _u32)]
 
 
 class HrrWorkItem(ctypes.Structure):
@@ -203,6 +205,7 @@ class Hierarchy:
         self.depth = info.depth
         self.device_bytes = info.device_bytes
         self.box = list(info.box)
+        self.split = "pow2" if info.split == SPLIT_POW2 else "radix"
 
     def permutation(self) -> np.ndarray:
         out = np.empty(self.n_lights, np.uint32)
@@ -294,16 +297,21 @@ class Context:
         return out_k, out_v
 
     # -- hierarchy ------------------------------------------------------------
-    def build_hierarchy(self, lights_xyz, leaf_size: int = 1, box=None) -> Hierarchy:
+    def build_hierarchy(self, lights_xyz, leaf_size: int = 1, box=None,
+                        split: str = "radix") -> Hierarchy:
+        """split: "radix" (highest differing Morton bit) or "pow2" (left child =
+        largest power of two below the node's length)."""
         lights = np.ascontiguousarray(lights_xyz, dtype=np.float32).reshape(-1, 3)
         bx = None if box is None else np.ascontiguousarray(box, dtype=np.float32)
         h = _P()
         _check(_lib.hrr_build_hierarchy(self.handle, lights.ctypes.data_as(_P), lights.shape[0],
-                                        leaf_size, None if bx is None else bx.ctypes.data_as(_P),
+                                        leaf_size | _SPLITS[split],
+                                        None if bx is None else bx.ctypes.data_as(_P),
                                         ctypes.byref(h)), "hrr_build_hierarchy")
         return Hierarchy(self, h.value)
 
-    def build_hierarchy_device(self, lights_xyz, leaf_size: int = 1, box=None, stream=None) -> Hierarchy:
+    def build_hierarchy_device(self, lights_xyz, leaf_size: int = 1, box=None, stream=None,
+                               split: str = "radix") -> Hierarchy:
         """The same hierarchy built on the GPU from a (n, 3) float32 cuda tensor."""
         import torch
         if not (lights_xyz.is_cuda and lights_xyz.dtype == torch.float32 and lights_xyz.is_contiguous()
@@ -312,7 +320,8 @@ class Context:
         bx = None if box is None else np.ascontiguousarray(box, dtype=np.float32)
         h = _P()
         _check(_lib.hrr_build_hierarchy_device(self.handle, _dptr(lights_xyz), lights_xyz.shape[0],
-                                               leaf_size, None if bx is None else bx.ctypes.data_as(_P),
+                                               leaf_size | _SPLITS[split],
+                                               None if bx is None else bx.ctypes.data_as(_P),
                                                _stream_handle(stream), ctypes.byref(h)),
                "hrr_build_hierarchy_device")
         return Hierarchy(self, h.value)

@@ -239,12 +239,14 @@ HRR_EXPORT hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint3
 // hierarchy
 // ---------------------------------------------------------------------------
 
-HRR_EXPORT hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz, uint32_t n_lights, uint32_t leaf_size,
+HRR_EXPORT hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz, uint32_t n_lights, uint32_t leaf_arg,
                                           const float* box, hrr_hierarchy** out) {
     if (!ctx || !out) return fail(HRR_E_INVALID, "hrr_build_hierarchy: null argument");
     *out = nullptr;
     if (n_lights > 0 && !lights_xyz) return fail(HRR_E_INVALID, "hrr_build_hierarchy: null lights");
-    if (leaf_size < 1 || leaf_size > 8) return fail(HRR_E_INVALID, "leaf_size must be in [1, 8]");
+    uint32_t leaf_size, split;
+    if (!parse_leaf_arg(leaf_arg, &leaf_size, &split))
+        return fail(HRR_E_INVALID, "leaf_size must be in [1, 8], optionally with HRR_SPLIT_POW2");
     if (n_lights >= kMaxNodes) return fail(HRR_E_INVALID, "at most %u lights", kMaxNodes - 1);
     if (box) {
         for (int k = 0; k < 3; ++k)
@@ -252,7 +254,7 @@ HRR_EXPORT hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz,
                 return fail(HRR_E_INVALID, "box must be finite with hi > lo");
     }
     HostHierarchy H;
-    if (!build_hierarchy(lights_xyz, n_lights, leaf_size, box, H))
+    if (!build_hierarchy(lights_xyz, n_lights, leaf_size, split == HRR_SPLIT_POW2, box, H))
         return fail(HRR_E_INVALID, "non-finite light coordinate");
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -260,6 +262,7 @@ HRR_EXPORT hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz,
     h->owner = ctx;
     h->n_lights = n_lights;
     h->leaf_size = leaf_size;
+    h->split = split;
     h->n_nodes = (uint32_t)H.nodes.size();
     h->depth = H.depth;
     memcpy(h->box, H.box, sizeof h->box);
@@ -295,6 +298,7 @@ HRR_EXPORT hrr_status hrr_hierarchy_get_info(const hrr_hierarchy* h, hrr_hierarc
     out->depth = h->depth;
     out->device_bytes = h->device_bytes;
     memcpy(out->box, h->box, sizeof out->box);
+    out->split = h->split;
     return HRR_OK;
 }
 
@@ -502,8 +506,11 @@ HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs,
     hipStream_t st = (hipStream_t)stream;
     hrr_eyes probe = *eyes;
     if (max_probe_eyes && probe.n > max_probe_eyes) probe.n = max_probe_eyes;
+    // candidates in order of preference: a later one must be more than 2 %
+    // faster to win, so that probe noise does not trade resident waves for a
+    // larger stack (1024 entries halve the waves per SIMD of a full launch)
     static const uint32_t epws[] = {1, 2, 4, 8};
-    static const uint32_t caps[] = {256, 512, 1024};
+    static const uint32_t caps[] = {512, 256, 1024};
     TuneVal bestv{0, 0, 0, 1e30f};
     DevBuf out;
     hipEvent_t e0, e1;
@@ -551,7 +558,7 @@ HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs,
                     result = r;
                     break;
                 }
-                if (ms_best < bestv.ms) bestv = TuneVal{epw, cap, h->leaf_size, ms_best};
+                if (ms_best < bestv.ms * 0.98f) bestv = TuneVal{epw, cap, h->leaf_size, ms_best};
             }
     }
     (void)hipEventDestroy(e0);

@@ -11,7 +11,9 @@
 //   order  : ascending (code, original index);
 //   split  : a node [a,b) with more than leaf_size lights is cut at the first
 //            index whose code has the highest bit where code[a] and
-//            code[b-1] differ; equal codes are cut at the midpoint;
+//            code[b-1] differ; equal codes are cut at the midpoint.  The
+//            power-of-two rule cuts after a + 2^k, 2^k the largest power of
+//            two below b - a (every left child an aligned index block);
 //   boxes  : exact fp32 min/max of the lights below each child.
 #include <stdint.h>
 
@@ -78,10 +80,16 @@ struct Builder {
     const std::vector<uint64_t>& code;
     const std::vector<float>& xyz;   // sorted
     uint32_t leaf;
+    bool pow2;
     std::vector<Node>& nodes;
     uint32_t depth_max = 0;
 
     uint32_t split(uint32_t a, uint32_t b) const {
+        if (pow2) {
+            const uint32_t len = b - a;
+            const uint32_t k = 1u << (31 - __builtin_clz(len - 1u));   // largest 2^k < len (len >= 2)
+            return a + k;
+        }
         const uint64_t ca = code[a], cb = code[b - 1];
         if (ca == cb) return a + (b - a) / 2;
         const int h = 63 - __builtin_clzll(ca ^ cb);
@@ -128,7 +136,7 @@ uint64_t morton_code(float x, float y, float z, const float* box) {
            spread_bits3(cell21(z, bx[2], bx[5]));
 }
 
-bool build_hierarchy(const float* xyz, uint32_t n, uint32_t leaf, const float* box, HostHierarchy& out) {
+bool build_hierarchy(const float* xyz, uint32_t n, uint32_t leaf, bool pow2, const float* box, HostHierarchy& out) {
     for (size_t q = 0; q < 3 * (size_t)n; ++q)
         if (!std::isfinite(xyz[q])) return false;
     struct Key {
@@ -143,6 +151,7 @@ bool build_hierarchy(const float* xyz, uint32_t n, uint32_t leaf, const float* b
     });
     out.n_lights = n;
     out.leaf_size = leaf;
+    out.pow2 = pow2;
     out.perm.resize(n);
     out.sorted_xyz.resize(3 * (size_t)n);
     std::vector<uint64_t> code(n);
@@ -158,7 +167,7 @@ bool build_hierarchy(const float* xyz, uint32_t n, uint32_t leaf, const float* b
         return true;
     }
     out.nodes.reserve(n > leaf ? (size_t)(2 * (n / leaf) + 2) : 1);
-    Builder B{code, out.sorted_xyz, leaf, out.nodes};
+    Builder B{code, out.sorted_xyz, leaf, pow2, out.nodes};
     const Box root = B.build(0, n, 0);
     out.depth = B.depth_max;
     for (int k = 0; k < 3; ++k) {

@@ -11,6 +11,7 @@ namespace hrr {
 
 struct HostHierarchy {
     uint32_t n_lights = 0, leaf_size = 1, depth = 0;
+    bool pow2 = false;                // split rule: largest power of two below the length
     std::vector<Node> nodes;          // internal nodes, preorder
     std::vector<float> sorted_xyz;    // 3 per light, sequence order
     std::vector<uint32_t> perm;       // perm[i] = original index of sequence index i
@@ -19,7 +20,7 @@ struct HostHierarchy {
 
 uint64_t morton_code(float x, float y, float z, const float* box);
 
-// false if a coordinate is not finite
-bool build_hierarchy(const float* xyz, uint32_t n, uint32_t leaf, const float* box, HostHierarchy& out);
+// false if a coordinate is not finite; pow2 selects the power-of-two split
+bool build_hierarchy(const float* xyz, uint32_t n, uint32_t leaf, bool pow2, const float* box, HostHierarchy& out);
 
 }  // namespace hrr

@@ -1,7 +1,8 @@
 // hrr_build_device.hip -- the light hierarchy built on the GPU, record for
 // record identical to the host builder (hrr_build.cpp): same Morton codes,
-// same (code, original index) order, same radix split (midpoint for equal
-// codes), same exact fp32 boxes and the same depth-first preorder numbering.
+// same (code, original index) order, same split rule (radix split with the
+// midpoint for equal codes, or the power-of-two split), same exact fp32 boxes
+// and the same depth-first preorder numbering.
 //
 // Section 1 of the paper only needs the lights sorted by a spatial hierarchy
 // with every node a contiguous index range; building it on the device lets a
@@ -76,7 +77,9 @@ __global__ void gather_kernel(const float* __restrict__ xyz, const uint32_t* __r
 // split c, end b, children t (or -1 for a leaf child), subtree counts,
 // preorder numbers and the node's own box.
 
-__device__ __forceinline__ uint32_t split_of(const uint64_t* __restrict__ code, uint32_t a, uint32_t b) {
+__device__ __forceinline__ uint32_t split_of(const uint64_t* __restrict__ code, uint32_t a, uint32_t b,
+                                             uint32_t pow2) {
+    if (pow2) return a + (1u << (31 - __clz((int)(b - a - 1u))));   // largest 2^k < b - a (b - a >= 2)
     const uint64_t ca = code[a], cb = code[b - 1];
     if (ca == cb) return a + (b - a) / 2;
     const int h = 63 - __clzll((long long)(ca ^ cb));
@@ -91,11 +94,11 @@ __device__ __forceinline__ uint32_t split_of(const uint64_t* __restrict__ code, 
 
 // Pass 1 of a level: split, count internal children.
 __global__ void split_kernel(Bfs T, const uint64_t* __restrict__ code, uint32_t t0, uint32_t t1, uint32_t leaf,
-                             uint32_t* __restrict__ kids) {
+                             uint32_t pow2, uint32_t* __restrict__ kids) {
     const uint32_t t = t0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= t1) return;
     const uint32_t a = T.a[t], b = T.b[t];
-    const uint32_t c = split_of(code, a, b);
+    const uint32_t c = split_of(code, a, b, pow2);
     T.c[t] = c;
     kids[t - t0] = (c - a > leaf ? 1u : 0u) + (b - c > leaf ? 1u : 0u);
 }
@@ -274,8 +277,8 @@ extern "C" hipError_t hrr_dev_init_root(Bfs T, uint32_t n, hipStream_t stream) {
 }
 
 extern "C" hipError_t hrr_dev_split(Bfs T, const uint64_t* code, uint32_t t0, uint32_t t1, uint32_t leaf,
-                                    uint32_t* kids, hipStream_t stream) {
-    split_kernel<<<blocks_for(t1 - t0), kThreads, 0, stream>>>(T, code, t0, t1, leaf, kids);
+                                    uint32_t pow2, uint32_t* kids, hipStream_t stream) {
+    split_kernel<<<blocks_for(t1 - t0), kThreads, 0, stream>>>(T, code, t0, t1, leaf, pow2, kids);
     return hipGetLastError();
 }
 

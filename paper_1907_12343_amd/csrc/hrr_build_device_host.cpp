@@ -26,7 +26,7 @@ extern "C" hipError_t hrr_dev_gather(const float* xyz, const uint32_t* perm, uin
                                      hipStream_t stream);
 extern "C" hipError_t hrr_dev_init_root(Bfs T, uint32_t n, hipStream_t stream);
 extern "C" hipError_t hrr_dev_split(Bfs T, const uint64_t* code, uint32_t t0, uint32_t t1, uint32_t leaf,
-                                    uint32_t* kids, hipStream_t stream);
+                                    uint32_t pow2, uint32_t* kids, hipStream_t stream);
 extern "C" hipError_t hrr_dev_place(Bfs T, uint32_t t0, uint32_t t1, uint32_t leaf, const uint32_t* prefix,
                                     uint32_t cap, hipStream_t stream);
 extern "C" hipError_t hrr_dev_refit(Bfs T, const float4* lights, uint32_t t0, uint32_t t1, hipStream_t stream);
@@ -56,13 +56,15 @@ struct Temps {
 }  // namespace
 
 HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* lights_xyz_dev, uint32_t n_lights,
-                                                 uint32_t leaf_size, const float* box, void* stream_v,
+                                                 uint32_t leaf_arg, const float* box, void* stream_v,
                                                  hrr_hierarchy** out) {
     using namespace hrr;
     if (!ctx || !out) return fail(HRR_E_INVALID, "hrr_build_hierarchy_device: null argument");
     *out = nullptr;
     if (n_lights > 0 && !lights_xyz_dev) return fail(HRR_E_INVALID, "hrr_build_hierarchy_device: null lights");
-    if (leaf_size < 1 || leaf_size > 8) return fail(HRR_E_INVALID, "leaf_size must be in [1, 8]");
+    uint32_t leaf_size, split;
+    if (!parse_leaf_arg(leaf_arg, &leaf_size, &split))
+        return fail(HRR_E_INVALID, "leaf_size must be in [1, 8], optionally with HRR_SPLIT_POW2");
     if (n_lights >= kMaxNodes) return fail(HRR_E_INVALID, "at most %u lights", kMaxNodes - 1);
     float qbox[6] = {0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
     if (box) {
@@ -81,6 +83,7 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
     h->owner = ctx;
     h->n_lights = n;
     h->leaf_size = leaf_size;
+    h->split = split;
     h->host_copies = false;
     auto fail_free = [&](hrr_status st) {
         hrr_free_hierarchy(ctx, h);
@@ -145,7 +148,7 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
         off.push_back(1);
         while (t1 > t0) {
             const uint32_t m = t1 - t0;
-            if ((e = hrr_dev_split(T, code, t0, t1, leaf_size, kids, stream)) != hipSuccess ||
+            if ((e = hrr_dev_split(T, code, t0, t1, leaf_size, split == HRR_SPLIT_POW2 ? 1u : 0u, kids, stream)) != hipSuccess ||
                 (e = hrr_dev_exclusive_sum(scan_tmp, &scan_bytes, kids, prefix, m, stream)) != hipSuccess ||
                 (e = hipMemcpyAsync(pin, prefix + (m - 1), sizeof(uint32_t), hipMemcpyDeviceToHost, stream)) !=
                     hipSuccess ||

@@ -16,6 +16,7 @@
 struct hrr_hierarchy {
     hrr_ctx* owner = nullptr;
     uint32_t n_lights = 0, leaf_size = 1, n_nodes = 0, depth = 0;
+    uint32_t split = HRR_SPLIT_RADIX;
     float box[6] = {0, 0, 0, 0, 0, 0};
     hrr::Node* d_nodes = nullptr;
     float* d_lights = nullptr;       // float4 per light
@@ -112,6 +113,14 @@ hrr_status fail(hrr_status st, const char* fmt, ...);
 hrr_status hip_fail(hipError_t e, const char* what);
 
 int ilog2_floor(uint64_t x);
+
+// Leaf size and split rule of a build's leaf_size argument; false if a bit
+// outside the leaf size (1..8) and HRR_SPLIT_POW2 is set.
+inline bool parse_leaf_arg(uint32_t arg, uint32_t* leaf, uint32_t* split) {
+    *leaf = arg & 0xFFu;
+    *split = arg & HRR_SPLIT_POW2;
+    return (arg & ~(0xFFu | HRR_SPLIT_POW2)) == 0 && *leaf >= 1 && *leaf <= 8;
+}
 
 // Resolve launch parameters (eyes per wave, stack entries) from options, the
 // tuner (an entry of the same or a neighbouring light class) and the built-in

@@ -62,14 +62,14 @@ HARNESS = r"""
 #include <cstdlib>
 #include <vector>
 #include "hrr_build.hpp"
-// reads: n leaf then 3n floats on stdin; writes perm, then nodes, then depth
+// reads: n leaf pow2 then 3n floats on stdin; writes perm, then nodes, then depth
 int main() {
-    unsigned n, leaf;
-    if (scanf("%u %u", &n, &leaf) != 2) return 2;
+    unsigned n, leaf, pow2;
+    if (scanf("%u %u %u", &n, &leaf, &pow2) != 3) return 2;
     std::vector<float> xyz(3 * (size_t)n);
     for (auto& v : xyz) if (scanf("%a", &v) != 1) return 3;
     hrr::HostHierarchy H;
-    if (!hrr::build_hierarchy(xyz.data(), n, leaf, nullptr, H)) return 4;
+    if (!hrr::build_hierarchy(xyz.data(), n, leaf, pow2 != 0, nullptr, H)) return 4;
     printf("%zu %u\n", H.nodes.size(), H.depth);
     for (unsigned i = 0; i < n; ++i) printf("%u\n", H.perm[i]);
     for (auto& d : H.nodes) {
@@ -94,8 +94,8 @@ def build_harness(tmp_path_factory):
     return str(exe)
 
 
-def _run_builder(exe, lights, leaf):
-    inp = "%d %d\n" % (lights.shape[0], leaf) + "\n".join(
+def _run_builder(exe, lights, leaf, pow2=False):
+    inp = "%d %d %d\n" % (lights.shape[0], leaf, int(pow2)) + "\n".join(
         " ".join(float(v).hex() for v in row) for row in lights) + "\n"
     out = subprocess.run([exe], input=inp, capture_output=True, text=True, check=True).stdout
     lines = out.splitlines()
@@ -112,14 +112,19 @@ def _run_builder(exe, lights, leaf):
     return perm, nodes, depth
 
 
+@pytest.mark.parametrize("pow2", [False, True])
 @pytest.mark.parametrize("n,leaf,seed", [(1, 1, 1), (2, 1, 2), (300, 1, 3), (300, 3, 4),
-                                         (1000, 8, 5), (64, 2, 6)])
-def test_host_builder_matches_oracle_order_and_is_valid(orc, build_harness, n, leaf, seed):
+                                         (1000, 8, 5), (64, 2, 6), (1024, 1, 7)])
+def test_host_builder_matches_oracle_order_and_is_valid(orc, build_harness, n, leaf, seed, pow2):
+    """Order = the oracle's Morton order; every split follows its rule (radix:
+    the highest differing code bit, midpoint for equal codes; power of two:
+    the left child holds the largest power of two below the length); exact
+    child boxes; preorder numbering; the recorded depth."""
     if seed == 6:   # many coincident lights: equal codes split at the midpoint
         lights = np.repeat(synth.uniform_points(8, seed), 8, axis=0)
     else:
         lights = synth.mixture_points(n, synth.mixture_centers(seed), seed + 100)
-    perm, nodes, depth = _run_builder(build_harness, lights, leaf)
+    perm, nodes, depth = _run_builder(build_harness, lights, leaf, pow2)
     assert np.array_equal(perm, orc.morton_order(lights))
     ls = lights[perm]
     codes = [orc.morton(*p) for p in ls]
@@ -134,7 +139,11 @@ def test_host_builder_matches_oracle_order_and_is_valid(orc, build_harness, n, l
         seen.add(idx)
         na, c, nb, right, lo_l, hi_l, lo_r, hi_r = nodes[idx]
         assert (na, nb) == (a, b) and a < c < b
-        if codes[a] == codes[b - 1]:
+        if pow2:
+            k = 1 << ((b - a - 1).bit_length() - 1)   # largest power of two below b - a
+            assert c - a == k and k < b - a <= 2 * k
+            assert a % k == 0 or n & (n - 1)          # aligned blocks when n is a power of two
+        elif codes[a] == codes[b - 1]:
             assert c == a + (b - a) // 2
         else:
             h = (codes[a] ^ codes[b - 1]).bit_length() - 1

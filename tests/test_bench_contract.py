@@ -30,15 +30,20 @@ def test_source_digest_ignores_comments_only(tmp_path, monkeypatch):
 
 
 def test_traffic_record_is_used_only_for_matching_sources(tmp_path):
-    args = argparse.Namespace(traffic_kib=None)
-    rec = {"kernel_sources_sha256": bench.kernel_source_digest(),
+    args = argparse.Namespace(traffic_kib=None, split="pow2")
+    rec = {"kernel_sources_sha256": bench.kernel_source_digest(), "split": "pow2",
            "fetch_kib_scaled": 1000.0, "write_kib_scaled": 24.0}
     f = tmp_path / "traffic.json"
     f.write_text(json.dumps(rec))
-    assert bench._traffic_bytes(args, path=str(f)) == 1024.0 * 1024.0
+    assert bench._traffic_bytes(args, path=str(f), split="pow2") == 1024.0 * 1024.0
+    assert bench._traffic_bytes(args, path=str(f), split="radix") is None   # another hierarchy
+    assert bench._traffic_bytes(args, path=str(f)) == 1024.0 * 1024.0       # not keyed (range min)
+    del rec["split"]
+    f.write_text(json.dumps(rec))
+    assert bench._traffic_bytes(args, path=str(f), split="pow2") is None    # unkeyed = radix
     rec["kernel_sources_sha256"] = "0" * 64
     f.write_text(json.dumps(rec))
     assert bench._traffic_bytes(args, path=str(f)) is None
     assert bench._traffic_bytes(args, path=str(tmp_path / "missing.json")) is None
-    over = argparse.Namespace(traffic_kib=[3.0, 1.0])
+    over = argparse.Namespace(traffic_kib=[3.0, 1.0], split="radix")
     assert bench._traffic_bytes(over, path=str(f)) == 4096.0

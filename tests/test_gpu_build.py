@@ -56,15 +56,17 @@ def _cases():
     return {k: np.ascontiguousarray(v, np.float32) for k, v in cases.items()}
 
 
+@pytest.mark.parametrize("split", ["radix", "pow2"])
 @pytest.mark.parametrize("leaf", [1, 2, 4, 8])
-def test_device_build_equals_host_build(ctx, leaf):
+def test_device_build_equals_host_build(ctx, leaf, split):
     for name, lights in _cases().items():
-        hh = ctx.build_hierarchy(lights, leaf_size=leaf)
-        hd = ctx.build_hierarchy_device(_dev(ctx, lights), leaf_size=leaf)
+        hh = ctx.build_hierarchy(lights, leaf_size=leaf, split=split)
+        hd = ctx.build_hierarchy_device(_dev(ctx, lights), leaf_size=leaf, split=split)
+        assert hh.split == hd.split == split
         try:
             _same(hh, hd)
         except AssertionError as ex:
-            raise AssertionError("case %s leaf %d: %s" % (name, leaf, ex))
+            raise AssertionError("case %s leaf %d %s: %s" % (name, leaf, split, ex))
         hh.free()
         hd.free()
 
@@ -82,10 +84,11 @@ def test_device_build_with_a_box_and_empty(ctx):
         h.free()
 
 
-def test_device_build_frame_scale(ctx):
+@pytest.mark.parametrize("split", ["radix", "pow2"])
+def test_device_build_frame_scale(ctx, split):
     fr = synth.frame()
-    hh = ctx.build_hierarchy(fr["lights"], leaf_size=1)
-    hd = ctx.build_hierarchy_device(_dev(ctx, fr["lights"]), leaf_size=1)
+    hh = ctx.build_hierarchy(fr["lights"], leaf_size=1, split=split)
+    hd = ctx.build_hierarchy_device(_dev(ctx, fr["lights"]), leaf_size=1, split=split)
     _same(hh, hd)
     hh.free()
     hd.free()
@@ -99,6 +102,11 @@ def test_device_build_rejects_bad_input(ctx, hrr):
     assert ei.value.status == hrr.HRR_E_INVALID
     with pytest.raises(hrr.HrrError):
         ctx.build_hierarchy_device(_dev(ctx, bad[:10]), leaf_size=0)
+    for arg in (0x200 | 1, 0x100, 9 | 0x100, 1 << 31):   # unknown flag bits, leaf size 0 or 9
+        with pytest.raises(hrr.HrrError):
+            ctx.build_hierarchy_device(_dev(ctx, bad[:10]), leaf_size=arg)
+        with pytest.raises(hrr.HrrError):
+            ctx.build_hierarchy(bad[:10], leaf_size=arg)
 
 
 def test_traversal_on_device_built_hierarchy(ctx, orc):

@@ -67,6 +67,21 @@ def test_tiny_full_parity(ctx, tiny, tiny_oracle, method, leaf, epw):
     h.free()
 
 
+@pytest.mark.parametrize("method", [0, 1, 4])
+@pytest.mark.parametrize("leaf", [1, 2, 8])
+@pytest.mark.parametrize("epw", [1, 8])
+def test_tiny_full_parity_pow2_split(ctx, tiny, tiny_oracle, method, leaf, epw):
+    """The accepted set does not depend on how the hierarchy splits its index
+    ranges: power-of-two splits (aligned blocks) give the oracle's set too."""
+    h = ctx.build_hierarchy(tiny["lights"], leaf_size=leaf, split="pow2")
+    assert h.split == "pow2"
+    pairs, n, _ = ctx.traverse_all(h, _eyes_t(ctx, tiny["eyes"]), tiny["s"], tiny["width"],
+                                   rmq_method=method, eyes_per_wave=epw, stack_entries=512)
+    assert n == tiny_oracle["keys"].size
+    assert np.array_equal(pair_keys_from_gpu(pairs), tiny_oracle["keys"])
+    h.free()
+
+
 def test_stack_spills_to_device_memory(ctx, orc):
     # a wide survivor front (large s) against a 256-entry LDS stack
     lights = synth.uniform_points(1 << 15, 801)
@@ -376,6 +391,32 @@ def _assert_every_pair_passes_its_test(pairs, fr, perm, chunk=1 << 27):
         xi = (_bitrev32(i) + r) & 0xFFFFFFFF
         assert bool((xi.to(torch.float64) < torch.ceil(p.to(torch.float64) * two32)).all())
         del pc, j, i, e, lt, dx, dy, dz, d2, p, r, xi
+
+
+def test_frame_scale_sampled_pow2_split(ctx, orc):
+    """The frame against the power-of-two hierarchy of its 2^20 lights (every
+    node an aligned block): the same count as the radix hierarchy and sampled
+    eyes pair for pair against the oracle."""
+    import torch
+    fr = synth.frame()
+    hr = ctx.build_hierarchy(fr["lights"], leaf_size=1)
+    hp = ctx.build_hierarchy(fr["lights"], leaf_size=1, split="pow2")
+    perm = orc.morton_order(fr["lights"])
+    assert np.array_equal(hp.permutation(), perm)
+    eyes = _eyes_t(ctx, fr["eyes"])
+    n_eyes = fr["eyes"].shape[0]
+    n = ctx.count(hr, eyes, fr["s"], fr["width"])
+    assert ctx.count(hp, eyes, fr["s"], fr["width"]) == n
+    pairs, n1, _ = ctx.traverse(hp, eyes, fr["s"], fr["width"], capacity=n)
+    assert n1 == n
+    sel = np.unique(np.concatenate([np.arange(7, n_eyes, 4099), [n_eyes - 1]]))
+    out = orc.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], fr["lights"][perm],
+                          fr["s"], lists=True)
+    assert np.array_equal(select_pairs_of_eyes(pairs, sel), pair_keys_from_oracle(out, sel))
+    del pairs
+    torch.cuda.empty_cache()
+    hr.free()
+    hp.free()
 
 
 def test_frame_scale_sampled(ctx, orc):
