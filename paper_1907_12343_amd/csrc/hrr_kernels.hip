@@ -534,9 +534,12 @@ __device__ __forceinline__ void leaf_lights(OutState& O, const ItemDesc& D, cons
 // The walk is bound by instruction issue and the vector-memory pipeline, so
 // resident waves matter more than a few spilled registers: ask for 8 waves
 // per SIMD (at most 64 VGPRs) for the one-eye-per-wave form (frame: 145 ms
-// against 147 ms with 7 waves and 157 ms with 5).
+// against 147 ms with 7 waves and 157 ms with 5).  The form that also writes
+// 1/p weights would spill inside the loop at 64 VGPRs: it asks for 7
+// (frame with weights 164.7 -> 145.4 ms; 148 ms with 6).
 template <int EPW, int METHOD, bool STATS, bool W>
-__global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(EPW == 1 ? 8 : 1, 8)))
+__global__ __launch_bounds__(kWave * kWavesPerBlock)
+__attribute__((amdgpu_waves_per_eu(EPW == 1 ? (W ? 7 : 8) : 1, 8)))
 void traverse_kernel(TravArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     // dynamic LDS: task table (n_items + 1 entries, padded to 16 bytes), then one area per wave
