@@ -48,6 +48,27 @@ def test_library_exports_every_declared_symbol():
     assert public == _declared(), public ^ _declared()
 
 
+def test_binding_constants_equal_the_header():
+    """Status codes, range-minimum methods, split rules and launch flags of
+    the Python binding are the values include/hrr.h defines."""
+    import paper_1907_12343_amd as hrr
+    text = open(HEADER).read()
+    defines = {m.group(1): int(m.group(2), 0)
+               for m in re.finditer(r"#define (HRR_\w+) (0x[0-9a-fA-F]+|\d+)u", text)}
+    enum = {m.group(1): int(m.group(2)) for m in re.finditer(r"(HRR_(?:OK|E_\w+)) = (\d+)", text)}
+    pairs = {"HRR_RMQ_PAPER": hrr.RMQ_PAPER, "HRR_RMQ_DIRECT": hrr.RMQ_DIRECT,
+             "HRR_RMQ_PAPER_FULL": hrr.RMQ_PAPER_FULL, "HRR_RMQ_PAPER_LOOP": hrr.RMQ_PAPER_LOOP,
+             "HRR_RMQ_DYADIC": hrr.RMQ_DYADIC, "HRR_RMQ_PAPER_NO_REUSE": hrr.RMQ_PAPER_NO_REUSE,
+             "HRR_SPLIT_RADIX": hrr.SPLIT_RADIX, "HRR_SPLIT_POW2": hrr.SPLIT_POW2,
+             "HRR_F_STATS": hrr.F_STATS, "HRR_F_NO_REORDER": hrr.F_NO_REORDER,
+             "HRR_F_TIMING": hrr.F_TIMING}
+    for name, value in pairs.items():
+        assert defines[name] == value, name
+    for name in ("HRR_OK", "HRR_E_INVALID", "HRR_E_NOMEM", "HRR_E_OVERFLOW", "HRR_E_DEVICE",
+                 "HRR_E_NOTREADY", "HRR_E_CANCELLED", "HRR_E_BUSY"):
+        assert enum[name] == getattr(hrr, name), name
+
+
 def test_binding_signatures_cover_the_header():
     import importlib.util
     spec = importlib.util.spec_from_file_location(
