@@ -133,9 +133,12 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         vtotal += items[k].h->n_lights ? (uint64_t)items[k].eyes.n * n_samples : 0ull;
     }
     vbegin[n] = (uint32_t)std::min<uint64_t>(vtotal, 0xFFFFFFFFull);
-    // eye order key (hrr_layout.hpp)
+    // eye order key (hrr_layout.hpp), for launches with enough work to gain from it
+    double order_cost = 0.0;
+    for (size_t k = 0; k < n; ++k)
+        order_cost += (double)tasks_of[k] * epw * pow((double)std::max<uint32_t>(items[k].h->n_lights, 1u), 0.6);
     uint32_t bits = 0, rbits = 0;
-    if (reorder) order_key_bits(n, vtotal, ctx->tile_bits, &bits, &rbits);
+    if (reorder && order_pays(order_cost)) order_key_bits(n, vtotal, ctx->tile_bits, &bits, &rbits);
     const bool ordered = bits > 0;
     std::vector<OrderItem> oitems;
     if (ordered) {

@@ -543,7 +543,7 @@ def test_device_range_minimum_code_on_the_host(orc, rmq_harness):
 LAYOUT_HARNESS = r"""
 #include <cstdio>
 #include "hrr_layout.hpp"
-// stdin lines: "o n virtual_eyes tile_bits" | "q n tasks" | "c capacity waves" | "e n_lights"
+// stdin lines: "o n virtual_eyes tile_bits" | "q n tasks" | "c capacity waves" | "e n_lights" | "p cost"
 int main() {
     char op;
     unsigned long long a, b, c;
@@ -559,6 +559,8 @@ int main() {
             printf("%u\n", hrr::chunk_shift_for(a, b));
         } else if (op == 'e' && scanf("%llu", &a) == 1) {
             printf("%u\n", hrr::default_eyes_per_wave((uint32_t)a));
+        } else if (op == 'p' && scanf("%llu", &a) == 1) {
+            printf("%d\n", hrr::order_pays((double)a) ? 1 : 0);
         } else {
             return 1;
         }
@@ -617,3 +619,6 @@ def test_launch_layout_choices(layout_harness):
     # eyes per wave by hierarchy size: 8 below 2^16 lights, 4 below 2^17, then 1
     assert ask(["e 0", "e 1024", "e 65535", "e 65536", "e 131071", "e 131072", "e 1048576",
                 "e 4294967295"]) == [(8,), (8,), (8,), (4,), (4,), (1,), (1,), (1,)]
+    # eye ordering only for launches with enough work: the 4096 x 1024 case (cost 4096 x
+    # 1024^0.6 = 262144) goes unordered, 4096 frame eyes x 2^20 lights (16777216) ordered
+    assert ask(["p 262144", "p 2097151", "p 2097152", "p 16777216"]) == [(0,), (0,), (1,), (1,)]

@@ -108,15 +108,29 @@ def test_stack_spills_to_device_memory(ctx, orc):
     h.free()
 
 
-@pytest.mark.parametrize("epw", [1, 8])
-def test_processing_order_does_not_change_the_set(ctx, tiny, tiny_oracle, epw):
-    h = ctx.build_hierarchy(tiny["lights"], leaf_size=2)
-    eyes = _eyes_t(ctx, tiny["eyes"])
+@pytest.fixture(scope="module")
+def ordered_case(orc):
+    """A launch with enough work to be ordered (8192 eyes x 2^14 lights: cost
+    8192 x (2^14)^0.6 = 2.8e6, above the 2^21 at which the library orders)."""
+    lights = synth.uniform_points(1 << 14, 811)
+    eyes = synth.uniform_points(8192, 812)
+    tile = synth.dither_tile(100)
+    sel = np.arange(eyes.shape[0])
+    ls = lights[orc.morton_order(lights)]
+    out = orc.accept_eyes(eyes, sel, 64, 0, tile, ls, 1e-3, lists=True)
+    return dict(lights=lights, eyes=eyes, keys=pair_keys_from_oracle(out, sel))
+
+
+@pytest.mark.parametrize("epw", [1, 2, 4, 8])
+def test_processing_order_does_not_change_the_set(ctx, ordered_case, epw):
+    """Eye ordering on and off give the oracle's set (leaf size 2)."""
+    h = ctx.build_hierarchy(ordered_case["lights"], leaf_size=2)
+    eyes = _eyes_t(ctx, ordered_case["eyes"])
     for reorder in (True, False):
-        pairs, n, st = ctx.traverse_all(h, eyes, tiny["s"], tiny["width"], eyes_per_wave=epw,
+        pairs, n, st = ctx.traverse_all(h, eyes, 1e-3, 64, eyes_per_wave=epw,
                                         reorder=reorder, stats=True)
-        assert np.array_equal(pair_keys_from_gpu(pairs), tiny_oracle["keys"])
-        assert st["eyes"] == tiny["eyes"].shape[0]
+        assert np.array_equal(pair_keys_from_gpu(pairs), ordered_case["keys"]), reorder
+        assert st["eyes"] == ordered_case["eyes"].shape[0]
     h.free()
 
 
