@@ -1062,8 +1062,15 @@ __global__ __launch_bounds__(256) void compact_plan_kernel(const ItemDesc* __res
     }
 }
 
-constexpr uint32_t kMoveRun = 16;   // moved elements per thread and step
+constexpr uint32_t kMoveRun = 16;   // moved elements per lane and step
 
+// Two mappings of moved elements to lanes.  With chunks of 2^10 or more
+// pairs (long holes and data runs) each wave moves a block of kWave *
+// kMoveRun consecutive elements, lane l taking e0 + l, e0 + l + kWave, ...,
+// so the 64 lanes of one access read and write whole cache lines (frame:
+// 258 -> 95 us).  With smaller chunks a lane stepping by kWave would cross a
+// hole boundary, a dependent load, almost every step; there each lane moves
+// its own run of kMoveRun consecutive elements instead.
 __global__ __launch_bounds__(256) void compact_move_kernel(const ItemDesc* __restrict__ items) {
     const ItemDesc& D = items[blockIdx.y];
     const unsigned long long moved = D.counters[CNT_MOVED];
@@ -1076,14 +1083,18 @@ __global__ __launch_bounds__(256) void compact_move_kernel(const ItemDesc* __res
     uint2* out = reinterpret_cast<uint2*>(D.pairs);
     const uint2* sl = reinterpret_cast<const uint2*>(D.slack_pairs);
     const unsigned long long cap = D.capacity;
+    const unsigned long long tid = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool lanes = D.chunk_shift >= 10;   // uniform over the block (one item per blockIdx.y)
+    const unsigned long long stride = lanes ? kWave : 1ull;          // between a lane's elements
+    const unsigned long long span = lanes ? (unsigned long long)kWave * kMoveRun : kMoveRun;   // per step
+    const unsigned long long first = lanes ? (tid / kWave) * span + tid % kWave : tid * kMoveRun;
     const unsigned long long step = (unsigned long long)gridDim.x * blockDim.x * kMoveRun;
-    for (unsigned long long e0 = ((unsigned long long)blockIdx.x * blockDim.x + threadIdx.x) * kMoveRun; e0 < moved;
-         e0 += step) {
+    for (unsigned long long e0 = first; e0 < moved; e0 += step) {
         // moved < both totals, so the walks below stop inside the prefixes
         unsigned long long q = prefix_rank(Hs, g.P, e0);
         unsigned long long i = prefix_rank(Ds, nd, e0);
-        const unsigned long long e1 = umin64(e0 + kMoveRun, moved);
-        for (unsigned long long e = e0; e < e1; ++e) {
+        const unsigned long long e1 = umin64(e0 - (lanes ? tid % kWave : 0ull) + span, moved);
+        for (unsigned long long e = e0; e < e1; e += stride) {
             while (Hs[q + 1] <= e) ++q;
             while (Ds[i + 1] <= e) ++i;
             const unsigned long long dst = hole_lo(g, pl[2 * q], pl[2 * q + 1]) + (e - Hs[q]);
