@@ -7,8 +7,9 @@
 // arrays.  max_inflight worker threads each own a HIP stream and a launch
 // scratch set.  A free worker takes, under the server lock, the longest FIFO
 // prefix of the queue that fits its limits and the free arena, enqueues the
-// eye uploads and ONE traversal launch with one item per request, and waits
-// for it on its own stream; meanwhile another worker is already batching
+// eye uploads and the traversal of that batch -- one persistent launch per
+// eyes-per-wave group of its requests, one item per request -- and waits for
+// it on its own stream; meanwhile another worker is already batching
 // whatever arrived since.  Results stay in the arena until released; a
 // request whose output overflowed its reservation is put back at the head of
 // the queue with its exact count reserved.
@@ -72,7 +73,8 @@ using ReqPtr = std::shared_ptr<Request>;
 
 struct Slot {
     hipStream_t stream = nullptr;
-    LaunchScratch S;
+    LaunchScratch S[4];            // one per eyes-per-wave group of a batch
+    std::vector<uint64_t> counts;  // pair count of every request of the last batch
     std::thread th;
     float* h_stage = nullptr;      // pinned eye staging
     size_t h_stage_bytes = 0;
@@ -207,13 +209,48 @@ hrr_status run_batch(Server& sv, Slot& slot, const std::vector<ReqPtr>& batch) {
     hrr_traverse_opts o{};
     o.eyes_per_wave = sv.cfg.eyes_per_wave;
     resolve_shape(ctx, &o, max_lights, total_eyes, &epw, &cap);
+    // requests grouped by the eyes per wave of their own hierarchy (as a
+    // batched call does), unless the configuration fixes the shape
+    std::vector<size_t> group[4];
+    uint32_t group_epw[4] = {epw, 0, 0, 0};
+    int n_groups = 1;
+    if (o.eyes_per_wave == 0 && items.size() > 1) {
+        n_groups = 0;
+        for (uint32_t ge : {1u, 2u, 4u, 8u}) {
+            std::vector<size_t> g;
+            for (size_t k = 0; k < items.size(); ++k) {
+                uint32_t ke = 1, kc = 0;
+                resolve_shape(ctx, &o, items[k].h->n_lights, items[k].eyes.n, &ke, &kc);
+                if (ke == ge || (ge == 1u && !(ke == 2u || ke == 4u || ke == 8u))) g.push_back(k);
+            }
+            if (!g.empty()) {
+                group[n_groups] = std::move(g);
+                group_epw[n_groups] = ge;
+                ++n_groups;
+            }
+        }
+    } else {
+        for (size_t k = 0; k < items.size(); ++k) group[0].push_back(k);
+    }
     uint32_t* pairs = reinterpret_cast<uint32_t*>(sv.base);
-    hrr_status st = launch_items(ctx, slot.S, items, epw, cap, HRR_RMQ_PAPER, 1, 0, false, true, pairs, nullptr,
-                                 slot.stream);
-    if (st != HRR_OK) return st;
+    std::vector<HostItem> sub;
+    hrr_status st = HRR_OK;
+    int launched = 0;
+    for (int g = 0; g < n_groups && st == HRR_OK; ++g, ++launched) {
+        sub.clear();
+        for (size_t k : group[g]) sub.push_back(items[k]);
+        st = launch_items(ctx, slot.S[g], sub, group_epw[g], cap, HRR_RMQ_PAPER, 1, 0, false, true, pairs, nullptr,
+                          slot.stream);
+    }
+    // earlier launches may be running even when a later one failed
     if ((e = hipStreamSynchronize(slot.stream)) != hipSuccess) return hip_fail(e, "server traversal");
-    if ((st = finish_items(ctx, slot.S)) != HRR_OK) return st;
-    if (slot.S.error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", slot.S.error);
+    if (st != HRR_OK) return st;
+    slot.counts.assign(items.size(), 0);
+    for (int g = 0; g < launched; ++g) {
+        if ((st = finish_items(ctx, slot.S[g])) != HRR_OK) return st;
+        if (slot.S[g].error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", slot.S[g].error);
+        for (size_t q = 0; q < group[g].size(); ++q) slot.counts[group[g][q]] = slot.S[g].counts[q];
+    }
     return HRR_OK;
 }
 
@@ -249,7 +286,7 @@ void worker(Server* sv, Slot* slot) {
                     finish_request(*sv, r, RState::Failed, rc, msg.c_str());
                     continue;
                 }
-                const uint64_t cnt = slot->S.counts[k];
+                const uint64_t cnt = slot->counts[k];
                 if (r.n) {
                     double& e = sv->ppe[r.h];
                     const double obs = (double)cnt / r.n;
@@ -312,7 +349,7 @@ void stop_server(hrr_ctx* ctx) {
     (void)hipSetDevice(ctx->device);
     for (auto& s : sv->slots) {
         if (s->stream) (void)hipStreamSynchronize(s->stream);
-        release_scratch(s->S);
+        for (auto& S : s->S) release_scratch(S);
         if (s->h_stage) (void)hipHostFree(s->h_stage);
         if (s->stream) (void)hipStreamDestroy(s->stream);
     }
