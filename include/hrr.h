@@ -310,10 +310,13 @@ uint32_t hrr_tuned_leaf_size(const hrr_ctx* ctx, uint32_t n_lights);
  * The server owns one device arena of hbm_budget_bytes, allocated at start,
  * that holds the eyes of running requests and the pairs of finished ones
  * until they are released.  max_inflight worker threads (one HIP stream
- * each) repeatedly take as many queued requests as fit (FIFO; up to
- * max_batch_items requests and max_batch_eyes eyes, and as much arena as is
- * free) and run them as the items of ONE persistent traversal launch; while
- * one launch runs, newly arrived requests are batched into the next.  Each
+ * each) repeatedly take as many queued requests as fit (in arrival order; up
+ * to max_batch_items requests and max_batch_eyes eyes, and as much arena as
+ * is free; a request that does not fit is passed over by later ones that do
+ * until it has waited overtake_ms) and run them as the items of one
+ * persistent traversal launch per eyes-per-wave group (Section 1: every
+ * request is the culling of its eye set against one hierarchy); while one
+ * launch runs, newly arrived requests are batched into the next.  Each
  * request reserves output space from a running estimate of pairs per eye for
  * its hierarchy; a request whose count exceeds its reservation is re-run once
  * with the exact count reserved (hrr_ticket_info.launches > 1).
@@ -332,6 +335,10 @@ typedef struct hrr_server_config {
     uint32_t eyes_per_wave;      /* 0 = tuned / default by hierarchy size; else 1, 2, 4 or 8 */
     float pairs_per_eye_guess;   /* output reservation per eye before any request on a
                                     hierarchy has finished (> 0; adapted online) */
+    float overtake_ms;           /* a queued request that does not fit is skipped by later
+                                    requests that do, until it has waited this long; from then
+                                    on nothing behind it is admitted until it runs (>= 0,
+                                    finite; 0 = strict FIFO admission) */
 } hrr_server_config;
 
 typedef struct hrr_server_stats {

@@ -71,7 +71,7 @@ class HrrTuneResult(ctypes.Structure):
 class HrrServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", _u64), ("max_inflight", _u32), ("max_batch_eyes", _u32),
                 ("max_batch_items", _u32), ("eyes_per_wave", _u32),
-                ("pairs_per_eye_guess", _f32)]
+                ("pairs_per_eye_guess", _f32), ("overtake_ms", _f32)]
 
 
 class HrrServerStats(ctypes.Structure):
@@ -427,9 +427,10 @@ class Context:
     # -- serving ------------------------------------------------------------------
     def server_start(self, hbm_budget_bytes: int, max_inflight: int = 2,
                      max_batch_eyes: int = 1 << 20, max_batch_items: int = 64,
-                     eyes_per_wave: int = 0, pairs_per_eye_guess: float = 64.0):
+                     eyes_per_wave: int = 0, pairs_per_eye_guess: float = 64.0,
+                     overtake_ms: float = 100.0):
         cfg = HrrServerConfig(hbm_budget_bytes, max_inflight, max_batch_eyes, max_batch_items,
-                              eyes_per_wave, pairs_per_eye_guess)
+                              eyes_per_wave, pairs_per_eye_guess, overtake_ms)
         _check(_lib.hrr_server_start(self.handle, ctypes.byref(cfg)), "hrr_server_start")
 
     def server_stop(self):

@@ -135,6 +135,45 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
     *cap = c;
 }
 
+void group_by_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, const std::vector<HostItem>& items, bool per_item,
+                    std::vector<LaunchGroup>& out) {
+    out.clear();
+    auto shape_of = [&](const std::vector<size_t>& members, uint32_t* epw, uint32_t* cap) {
+        uint64_t max_eyes = 0;
+        uint32_t max_lights = 0;
+        for (size_t k : members) {
+            max_eyes = std::max<uint64_t>(max_eyes, items[k].eyes.n);
+            if (items[k].h) max_lights = std::max(max_lights, items[k].h->n_lights);
+        }
+        resolve_shape(ctx, opts, max_lights, max_eyes, epw, cap);
+    };
+    if (!per_item) {
+        LaunchGroup g;
+        g.items.resize(items.size());
+        for (size_t k = 0; k < items.size(); ++k) g.items[k] = k;
+        shape_of(g.items, &g.epw, &g.cap);
+        out.push_back(std::move(g));
+        return;
+    }
+    std::vector<uint32_t> item_epw(items.size(), 1u);
+    for (size_t k = 0; k < items.size(); ++k) {
+        uint32_t kc = 0;
+        if (items[k].h) resolve_shape(ctx, opts, items[k].h->n_lights, items[k].eyes.n, &item_epw[k], &kc);
+        const uint32_t ke = item_epw[k];
+        if (!(ke == 1 || ke == 2 || ke == 4 || ke == 8)) item_epw[k] = 1;
+    }
+    for (uint32_t ge : {1u, 2u, 4u, 8u}) {
+        LaunchGroup g;
+        for (size_t k = 0; k < items.size(); ++k)
+            if (item_epw[k] == ge) g.items.push_back(k);
+        if (g.items.empty()) continue;
+        uint32_t e_unused = 0;
+        shape_of(g.items, &e_unused, &g.cap);
+        g.epw = ge;
+        out.push_back(std::move(g));
+    }
+}
+
 static void fill_stats(const unsigned long long* st, hrr_stats* out) {
     out->eyes = st[ST_EYES];
     out->pairs = st[ST_PAIRS];
@@ -369,47 +408,16 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     const size_t n = items.size();
-    uint64_t max_eyes = 0;
-    uint32_t max_lights = 0;
-    for (auto& it : items) {
-        max_eyes = std::max<uint64_t>(max_eyes, it.eyes.n);
-        if (it.h) max_lights = std::max(max_lights, it.h->n_lights);
-    }
-    uint32_t epw, cap;
-    resolve_shape(ctx, opts, max_lights, max_eyes, &epw, &cap);
-    if (epw_override) epw = epw_override;
-    if (cap_override) cap = cap_override;
-
-    // groups of items (indices into `items`) and their eyes per wave
+    // groups of items and their launch shapes
     constexpr int kMaxGroups = 4;
-    std::vector<size_t> group[kMaxGroups];
-    uint32_t group_epw[kMaxGroups] = {0, 0, 0, 0};
-    int n_groups = 1;
     const bool per_item = n > 1 && epw_override == 0 && !(opts && opts->eyes_per_wave);
-    if (per_item) {
-        std::vector<uint32_t> item_epw(n, 1u);   // an item without a hierarchy fails in the first launch
-        for (size_t k = 0; k < n; ++k) {
-            uint32_t kc = 0;
-            if (items[k].h) resolve_shape(ctx, opts, items[k].h->n_lights, items[k].eyes.n, &item_epw[k], &kc);
-            const uint32_t ke = item_epw[k];
-            if (!(ke == 1 || ke == 2 || ke == 4 || ke == 8)) item_epw[k] = 1;
-        }
-        n_groups = 0;
-        for (uint32_t ge : {1u, 2u, 4u, 8u}) {
-            std::vector<size_t> g;
-            for (size_t k = 0; k < n; ++k)
-                if (item_epw[k] == ge) g.push_back(k);
-            if (!g.empty()) {
-                group[n_groups] = std::move(g);
-                group_epw[n_groups] = ge;
-                ++n_groups;
-            }
-        }
-    } else {
-        group[0].resize(n);
-        for (size_t k = 0; k < n; ++k) group[0][k] = k;
-        group_epw[0] = epw;
+    std::vector<LaunchGroup> groups;
+    group_by_shape(ctx, opts, items, per_item, groups);
+    for (auto& g : groups) {
+        if (epw_override) g.epw = epw_override;
+        if (cap_override) g.cap = cap_override;
     }
+    const int n_groups = (int)groups.size();
     LaunchScratch* scr[kMaxGroups] = {&ctx->scratch, &ctx->group_scratch[0], &ctx->group_scratch[1],
                                       &ctx->group_scratch[2]};
 
@@ -422,9 +430,9 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
     std::vector<HostItem> sub;
     for (int g = 0; g < n_groups; ++g) {
         sub.clear();
-        for (size_t k : group[g]) sub.push_back(items[k]);
-        const hrr_status st = launch_items(ctx, *scr[g], sub, group_epw[g], cap, method, ns, s0, want_stats, reorder,
-                                           pairs, weights, stream, timing);
+        for (size_t k : groups[g].items) sub.push_back(items[k]);
+        const hrr_status st = launch_items(ctx, *scr[g], sub, groups[g].epw, groups[g].cap, method, ns, s0,
+                                           want_stats, reorder, pairs, weights, stream, timing);
         if (st != HRR_OK) {
             // launches of earlier groups may be running: let them end before
             // the caller regains its buffers
@@ -443,8 +451,8 @@ static hrr_status run_sync(hrr_ctx* ctx, const std::vector<HostItem>& items, con
         LaunchScratch& S = *scr[g];
         hrr_status st = finish_items(ctx, S);
         if (st != HRR_OK) return st;
-        for (size_t q = 0; q < group[g].size(); ++q) {
-            const size_t k = group[g][q];
+        for (size_t q = 0; q < groups[g].items.size(); ++q) {
+            const size_t k = groups[g].items[q];
             counts[k] = S.counts[q];
             total += counts[k];
             if (counts[k] > items[k].out_capacity) overflow = true;

@@ -96,4 +96,40 @@ HRR_HD unsigned long long prefix_rank(const unsigned long long* prefix, unsigned
     return lo;
 }
 
+// Which moved elements a thread of compact_move_kernel handles.  Two
+// mappings over `threads` threads (a multiple of the 64-lane wave):
+//   run mode  (lanes = false): thread t takes the runs [t R, t R + R),
+//             [t R + T R, ...), ... of R = run consecutive elements, T the
+//             thread count;
+//   lane mode (lanes = true): wave w = t / 64 takes blocks of 64 R
+//             consecutive elements, [w 64 R, (w + 1) 64 R), then the block
+//             T R further on, and so on, and its lane l = t % 64 takes the
+//             elements l, l + 64, l + 128, ... of each block, so that the 64
+//             lanes of one access touch 64 consecutive elements.
+// Either way every element of [0, moved) belongs to exactly one thread.  A
+// thread walks its elements as: for (e0 = first; e0 < moved; e0 += step)
+// for (e = e0; e < run_end(e0); e += stride).
+struct MoveMap {
+    unsigned long long first;    // first element of the thread
+    unsigned long long stride;   // between the thread's elements inside one run or block
+    unsigned long long span;     // elements of one run (run mode) or block (lane mode)
+    unsigned long long step;     // from one run or block of the thread to its next
+    unsigned long long lane;     // offset of the thread inside its block (0 in run mode)
+};
+
+HRR_HD MoveMap move_map(bool lanes, unsigned long long tid, unsigned long long threads, unsigned long long run) {
+    MoveMap m;
+    m.lane = lanes ? tid % 64ull : 0ull;
+    m.stride = lanes ? 64ull : 1ull;
+    m.span = lanes ? 64ull * run : run;
+    m.first = lanes ? (tid / 64ull) * m.span + m.lane : tid * run;
+    m.step = threads * run;
+    return m;
+}
+
+// End (exclusive) of the run or block that starts the thread's walk at e0.
+HRR_HD unsigned long long move_run_end(const MoveMap& m, unsigned long long e0, unsigned long long moved) {
+    return umin64(e0 - m.lane + m.span, moved);
+}
+
 }  // namespace hrr

@@ -128,6 +128,20 @@ inline bool parse_leaf_arg(uint32_t arg, uint32_t* leaf, uint32_t* split) {
 void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes,
                    uint32_t* epw, uint32_t* cap);
 
+// The launches of a call of several items.  With per_item, the items are
+// grouped by the eyes per wave of their own shape (tuned or by hierarchy
+// size; groups in the order 1, 2, 4, 8 eyes per wave, i.e. largest
+// hierarchies first) and every group takes the stack size resolved for its
+// own largest hierarchy and eye set; otherwise one group holds every item
+// with the shape resolved for the largest of them.  Items without a
+// hierarchy go to the one-eye-per-wave group (their launch rejects them).
+struct LaunchGroup {
+    std::vector<size_t> items;
+    uint32_t epw = 1, cap = 512;
+};
+void group_by_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, const std::vector<HostItem>& items, bool per_item,
+                    std::vector<LaunchGroup>& out);
+
 // Enqueue one persistent launch of a set of items on `stream` with scratch
 // `S`: the eye order, the traversal, the compaction that makes every item's
 // stored pairs dense (on the device), and the readback of the counters.

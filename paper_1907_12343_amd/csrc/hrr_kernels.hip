@@ -1085,16 +1085,13 @@ __global__ __launch_bounds__(256) void compact_move_kernel(const ItemDesc* __res
     const unsigned long long cap = D.capacity;
     const unsigned long long tid = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x;
     const bool lanes = D.chunk_shift >= 10;   // uniform over the block (one item per blockIdx.y)
-    const unsigned long long stride = lanes ? kWave : 1ull;          // between a lane's elements
-    const unsigned long long span = lanes ? (unsigned long long)kWave * kMoveRun : kMoveRun;   // per step
-    const unsigned long long first = lanes ? (tid / kWave) * span + tid % kWave : tid * kMoveRun;
-    const unsigned long long step = (unsigned long long)gridDim.x * blockDim.x * kMoveRun;
-    for (unsigned long long e0 = first; e0 < moved; e0 += step) {
+    const MoveMap mm = move_map(lanes, tid, (unsigned long long)gridDim.x * blockDim.x, kMoveRun);
+    for (unsigned long long e0 = mm.first; e0 < moved; e0 += mm.step) {
         // moved < both totals, so the walks below stop inside the prefixes
         unsigned long long q = prefix_rank(Hs, g.P, e0);
         unsigned long long i = prefix_rank(Ds, nd, e0);
-        const unsigned long long e1 = umin64(e0 - (lanes ? tid % kWave : 0ull) + span, moved);
-        for (unsigned long long e = e0; e < e1; e += stride) {
+        const unsigned long long e1 = move_run_end(mm, e0, moved);
+        for (unsigned long long e = e0; e < e1; e += mm.stride) {
             while (Hs[q + 1] <= e) ++q;
             while (Ds[i + 1] <= e) ++i;
             const unsigned long long dst = hole_lo(g, pl[2 * q], pl[2 * q + 1]) + (e - Hs[q]);

@@ -5,14 +5,15 @@
 // Design.  One device arena (the HBM budget) is allocated at start and
 // carved by a first-fit allocator into request eye copies and result pair
 // arrays.  max_inflight worker threads each own a HIP stream and a launch
-// scratch set.  A free worker takes, under the server lock, the longest FIFO
-// prefix of the queue that fits its limits and the free arena, enqueues the
-// eye uploads and the traversal of that batch -- one persistent launch per
-// eyes-per-wave group of its requests, one item per request -- and waits for
-// it on its own stream; meanwhile another worker is already batching
-// whatever arrived since.  Results stay in the arena until released; a
-// request whose output overflowed its reservation is put back at the head of
-// the queue with its exact count reserved.
+// scratch set.  A free worker takes, under the server lock, the queued
+// requests that fit its limits and the free arena (hrr_admit.hpp: in arrival
+// order, passing over a request that does not fit until it has waited
+// overtake_ms), enqueues the eye uploads and the traversal of that batch --
+// one persistent launch per eyes-per-wave group of its requests, one item per
+// request -- and waits for it on its own stream; meanwhile another worker is
+// already batching whatever arrived since.  Results stay in the arena until
+// released; a request whose output overflowed its reservation is put back at
+// the head of the queue with its exact count reserved.
 #include <hip/hip_runtime_api.h>
 #include <math.h>
 #include <string.h>
@@ -29,6 +30,7 @@
 #include <unordered_map>
 #include <vector>
 
+#include "hrr_admit.hpp"
 #include "hrr_arena.hpp"
 #include "hrr_ctx.hpp"
 
@@ -41,6 +43,7 @@ namespace {
 constexpr uint64_t kAlign = Arena::kAlign;
 constexpr uint64_t kEyeBytes = 3 * sizeof(float);
 constexpr uint64_t kPairBytes = 2 * sizeof(uint32_t);
+constexpr uint32_t kAdmitScan = 256;   // queue entries the admission looks at per batch
 
 uint64_t round_up(uint64_t x) { return Arena::round_up(x); }
 
@@ -75,6 +78,8 @@ struct Slot {
     hipStream_t stream = nullptr;
     LaunchScratch S[4];            // one per eyes-per-wave group of a batch
     std::vector<uint64_t> counts;  // pair count of every request of the last batch
+    std::vector<hrr_status> status;   // outcome of every request of the last batch
+    std::vector<std::string> errs;    // and its message when it failed
     std::thread th;
     float* h_stage = nullptr;      // pinned eye staging
     size_t h_stage_bytes = 0;
@@ -129,45 +134,54 @@ void finish_request(Server& sv, Request& r, RState state, hrr_status status, con
     }
 }
 
-// Take the FIFO prefix of the queue that fits.  Called with sv.mu held.
+// Requests whose exact reservation (known after an overflow) can never fit
+// beside their eyes fail; then the admission policy picks the batch.  Called
+// with sv.mu held.
 void take_batch(Server& sv, std::vector<ReqPtr>& batch) {
-    uint64_t eyes = 0;
-    while (!sv.queue.empty() && batch.size() < sv.cfg.max_batch_items) {
-        ReqPtr r = sv.queue.front();
-        if (!batch.empty() && eyes + r->n > sv.cfg.max_batch_eyes) break;
-        const uint64_t ebytes = (uint64_t)r->n * kEyeBytes;
-        uint64_t want = reservation_for(sv, *r);
-        const uint64_t budget = sv.arena.size();
-        // never reserve more than could ever fit beside the eyes
-        const uint64_t room = budget > round_up(ebytes) + kAlign ? (budget - round_up(ebytes) - kAlign) / kPairBytes : 0;
-        if (want > room) {
-            if (r->exact) {
-                sv.queue.pop_front();
-                finish_request(sv, *r, RState::Failed, HRR_E_NOMEM,
-                               "result does not fit the server's device budget");
-                sv.cv_done.notify_all();
-                continue;
-            }
-            want = room;
+    const uint64_t budget = sv.arena.size();
+    auto room_of = [&](const Request& r) {
+        const uint64_t ebytes = (uint64_t)r.n * kEyeBytes;
+        return budget > round_up(ebytes) + kAlign ? (budget - round_up(ebytes) - kAlign) / kPairBytes : 0;
+    };
+    bool failed = false;
+    for (auto it = sv.queue.begin(); it != sv.queue.end();) {
+        Request& r = **it;
+        if (r.exact && r.reserve > room_of(r)) {
+            finish_request(sv, r, RState::Failed, HRR_E_NOMEM, "result does not fit the server's device budget");
+            it = sv.queue.erase(it);
+            failed = true;
+        } else {
+            ++it;
         }
-        uint64_t eoff = 0, ooff = 0;
-        if (ebytes && !sv.arena.alloc(ebytes, &eoff)) break;
-        if (want && !sv.arena.alloc(want * kPairBytes, &ooff)) {
-            if (ebytes) sv.arena.release(eoff, ebytes);
-            break;
-        }
-        sv.queue.pop_front();
-        r->eye_off = eoff;
-        r->eye_bytes = ebytes;
-        r->out_off = ooff;
-        r->out_bytes = want * kPairBytes;
-        r->reserve = want;
+    }
+    if (failed) sv.cv_done.notify_all();
+    // output reservation per queued request: the estimate, never more than
+    // could ever fit beside its eyes
+    std::vector<uint64_t> want;
+    want.reserve(std::min<size_t>(sv.queue.size(), kAdmitScan));
+    AdmitLimits L{sv.cfg.max_batch_items, sv.cfg.max_batch_eyes, (double)sv.cfg.overtake_ms * 1e-3, kAdmitScan};
+    std::vector<Admitted> picked;
+    admit_batch(sv.arena, L, now_s(), sv.queue.size(),
+                [&](size_t i) {
+                    const Request& r = *sv.queue[i];
+                    if (want.size() <= i) want.resize(i + 1, 0);
+                    want[i] = std::min(reservation_for(sv, r), room_of(r));
+                    return AdmitView{r.n, (uint64_t)r.n * kEyeBytes, want[i] * kPairBytes, r.submit_s};
+                },
+                picked);
+    for (const Admitted& a : picked) {
+        const ReqPtr& r = sv.queue[a.pos];
+        r->eye_off = a.eye_off;
+        r->eye_bytes = (uint64_t)r->n * kEyeBytes;
+        r->out_off = a.out_off;
+        r->out_bytes = want[a.pos] * kPairBytes;
+        r->reserve = want[a.pos];
         r->state = RState::Running;
         if (r->launches == 0) r->start_s = now_s();
         r->launches++;
-        eyes += r->n;
         batch.push_back(r);
     }
+    for (auto it = picked.rbegin(); it != picked.rend(); ++it) sv.queue.erase(sv.queue.begin() + (ptrdiff_t)it->pos);
 }
 
 // Enqueue uploads and one traversal launch for `batch`, wait for it and
@@ -188,8 +202,6 @@ hrr_status run_batch(Server& sv, Slot& slot, const std::vector<ReqPtr>& batch) {
     std::vector<HostItem> items;
     items.reserve(batch.size());
     size_t at = 0;
-    uint32_t max_lights = 0;
-    uint64_t total_eyes = 0;
     for (auto& r : batch) {
         const size_t bytes = (size_t)r->n * kEyeBytes;
         float* dev_eyes = bytes ? reinterpret_cast<float*>(sv.base + r->eye_off) : nullptr;
@@ -202,54 +214,45 @@ hrr_status run_batch(Server& sv, Slot& slot, const std::vector<ReqPtr>& batch) {
         at += bytes;
         hrr_eyes E{dev_eyes, r->n, r->width, r->offset, 0};
         items.push_back(HostItem{r->h, E, r->s, r->out_off / kPairBytes, r->reserve});
-        max_lights = std::max(max_lights, r->h->n_lights);
-        total_eyes += r->n;
     }
-    uint32_t epw = 0, cap = 0;
     hrr_traverse_opts o{};
     o.eyes_per_wave = sv.cfg.eyes_per_wave;
-    resolve_shape(ctx, &o, max_lights, total_eyes, &epw, &cap);
     // requests grouped by the eyes per wave of their own hierarchy (as a
-    // batched call does), unless the configuration fixes the shape
-    std::vector<size_t> group[4];
-    uint32_t group_epw[4] = {epw, 0, 0, 0};
-    int n_groups = 1;
-    if (o.eyes_per_wave == 0 && items.size() > 1) {
-        n_groups = 0;
-        for (uint32_t ge : {1u, 2u, 4u, 8u}) {
-            std::vector<size_t> g;
-            for (size_t k = 0; k < items.size(); ++k) {
-                uint32_t ke = 1, kc = 0;
-                resolve_shape(ctx, &o, items[k].h->n_lights, items[k].eyes.n, &ke, &kc);
-                if (ke == ge || (ge == 1u && !(ke == 2u || ke == 4u || ke == 8u))) g.push_back(k);
-            }
-            if (!g.empty()) {
-                group[n_groups] = std::move(g);
-                group_epw[n_groups] = ge;
-                ++n_groups;
-            }
-        }
-    } else {
-        for (size_t k = 0; k < items.size(); ++k) group[0].push_back(k);
-    }
+    // batched call does), unless the configuration fixes the shape; each
+    // group with the stack size of its own items
+    std::vector<LaunchGroup> groups;
+    group_by_shape(ctx, &o, items, o.eyes_per_wave == 0 && items.size() > 1, groups);
     uint32_t* pairs = reinterpret_cast<uint32_t*>(sv.base);
     std::vector<HostItem> sub;
-    hrr_status st = HRR_OK;
-    int launched = 0;
-    for (int g = 0; g < n_groups && st == HRR_OK; ++g, ++launched) {
+    std::vector<hrr_status> gst(groups.size(), HRR_OK);
+    std::vector<std::string> gmsg(groups.size());
+    for (size_t g = 0; g < groups.size(); ++g) {
         sub.clear();
-        for (size_t k : group[g]) sub.push_back(items[k]);
-        st = launch_items(ctx, slot.S[g], sub, group_epw[g], cap, HRR_RMQ_PAPER, 1, 0, false, true, pairs, nullptr,
-                          slot.stream);
+        for (size_t k : groups[g].items) sub.push_back(items[k]);
+        gst[g] = launch_items(ctx, slot.S[g], sub, groups[g].epw, groups[g].cap, HRR_RMQ_PAPER, 1, 0, false, true,
+                              pairs, nullptr, slot.stream);
+        if (gst[g] != HRR_OK) gmsg[g] = hrr_last_error(ctx);
     }
-    // earlier launches may be running even when a later one failed
+    // launches that were enqueued run to the end even when another failed
     if ((e = hipStreamSynchronize(slot.stream)) != hipSuccess) return hip_fail(e, "server traversal");
-    if (st != HRR_OK) return st;
+    // a group's failure fails only that group's requests
     slot.counts.assign(items.size(), 0);
-    for (int g = 0; g < launched; ++g) {
-        if ((st = finish_items(ctx, slot.S[g])) != HRR_OK) return st;
-        if (slot.S[g].error) return fail(HRR_E_DEVICE, "traversal kernel reported error %u", slot.S[g].error);
-        for (size_t q = 0; q < group[g].size(); ++q) slot.counts[group[g][q]] = slot.S[g].counts[q];
+    slot.status.assign(items.size(), HRR_OK);
+    slot.errs.assign(items.size(), std::string());
+    for (size_t g = 0; g < groups.size(); ++g) {
+        hrr_status st = gst[g];
+        if (st == HRR_OK) {
+            st = finish_items(ctx, slot.S[g]);
+            if (st == HRR_OK && slot.S[g].error)
+                st = fail(HRR_E_DEVICE, "traversal kernel reported error %u", slot.S[g].error);
+            if (st != HRR_OK) gmsg[g] = hrr_last_error(ctx);
+        }
+        for (size_t q = 0; q < groups[g].items.size(); ++q) {
+            const size_t k = groups[g].items[q];
+            slot.status[k] = st;
+            if (st == HRR_OK) slot.counts[k] = slot.S[g].counts[q];
+            else slot.errs[k] = gmsg[g];
+        }
     }
     return HRR_OK;
 }
@@ -280,10 +283,11 @@ void worker(Server* sv, Slot* slot) {
                 Request& r = *batch[k];
                 if (r.eye_bytes) sv->arena.release(r.eye_off, r.eye_bytes);
                 r.eye_bytes = 0;
-                if (rc != HRR_OK) {
+                const hrr_status rk = rc != HRR_OK ? rc : slot->status[k];
+                if (rk != HRR_OK) {
                     if (r.out_bytes) sv->arena.release(r.out_off, r.out_bytes);
                     r.out_bytes = 0;
-                    finish_request(*sv, r, RState::Failed, rc, msg.c_str());
+                    finish_request(*sv, r, RState::Failed, rk, rc != HRR_OK ? msg.c_str() : slot->errs[k].c_str());
                     continue;
                 }
                 const uint64_t cnt = slot->counts[k];
@@ -375,6 +379,8 @@ HRR_EXPORT hrr_status hrr_server_start(hrr_ctx* ctx, const hrr_server_config* cf
     if (cfg->hbm_budget_bytes < (1ull << 20)) return fail(HRR_E_INVALID, "hbm_budget_bytes must be >= 1 MiB");
     if (cfg->max_inflight < 1 || cfg->max_inflight > 8) return fail(HRR_E_INVALID, "max_inflight must be in [1, 8]");
     if (cfg->max_batch_eyes < 1) return fail(HRR_E_INVALID, "max_batch_eyes must be >= 1");
+    if (!(cfg->overtake_ms >= 0.0f) || !isfinite(cfg->overtake_ms))
+        return fail(HRR_E_INVALID, "overtake_ms must be finite and >= 0");
     if (cfg->max_batch_items < 1 || cfg->max_batch_items > kMaxItemsPerLaunch)
         return fail(HRR_E_INVALID, "max_batch_items must be in [1, %u]", kMaxItemsPerLaunch);
     const uint32_t epw = cfg->eyes_per_wave;

@@ -467,6 +467,102 @@ def test_output_compaction_fills_every_position(compact_harness, count, extra, s
         assert r.returncode == 0, r.stdout + r.stderr
 
 
+MOVEMAP_HARNESS = r"""
+#include <cstdio>
+#include <vector>
+#include "hrr_compact.hpp"
+// args: lanes threads run moved; walks every thread's elements exactly as
+// compact_move_kernel does and checks that each e in [0, moved) is visited once
+int main(int argc, char** argv) {
+    if (argc != 5) return 2;
+    const bool lanes = atoi(argv[1]) != 0;
+    const unsigned long long threads = strtoull(argv[2], 0, 10), run = strtoull(argv[3], 0, 10),
+                             moved = strtoull(argv[4], 0, 10);
+    std::vector<unsigned char> seen(moved, 0);
+    for (unsigned long long t = 0; t < threads; ++t) {
+        const hrr::MoveMap m = hrr::move_map(lanes, t, threads, run);
+        for (unsigned long long e0 = m.first; e0 < moved; e0 += m.step) {
+            const unsigned long long e1 = hrr::move_run_end(m, e0, moved);
+            for (unsigned long long e = e0; e < e1; e += m.stride) {
+                if (seen[e]++) { printf("element %llu visited twice (thread %llu)\n", e, t); return 1; }
+            }
+        }
+    }
+    for (unsigned long long e = 0; e < moved; ++e)
+        if (!seen[e]) { printf("element %llu never visited\n", e); return 1; }
+    printf("ok\n");
+    return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def movemap_harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("movemap")
+    src = d / "movemap.cpp"
+    src.write_text("#include <cstdlib>\n" + MOVEMAP_HARNESS)
+    exe = d / "movemap"
+    subprocess.run(["g++", "-O2", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    return str(exe)
+
+
+@pytest.mark.parametrize("lanes", [0, 1])
+@pytest.mark.parametrize("threads", [256, 1024, 4096, 256 * 23])
+@pytest.mark.parametrize("moved", [0, 1, 63, 64, 65, 1023, 1024, 1025, 16383, 16384, 16385, 100003, 1 << 18])
+def test_compaction_move_mapping_visits_each_element_once(movemap_harness, lanes, threads, moved):
+    """Both thread mappings of compact_move_kernel (per-lane runs for small
+    chunks, lane-interleaved blocks for chunks of 2^10 pairs or more) hand
+    every moved element to exactly one thread, for grids of 1 to 23 blocks
+    per item and moved counts around the run and block sizes."""
+    r = subprocess.run([movemap_harness, str(lanes), str(threads), "16", str(moved)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+
+
+BITS_HARNESS = r"""
+#include <cstdio>
+#include "hrr_rmq.hpp"
+// args: b k_r; prints b_h = fls(b), k_p = ffs(k_r), k_q = top bit of the lowest
+// run of ones of k_r, and m = k_r with the bits above b_h cleared, using the
+// bit primitives of the range-minimum code
+int main(int argc, char** argv) {
+    if (argc != 3) return 2;
+    const uint32_t b = (uint32_t)strtoul(argv[1], 0, 0), kr = (uint32_t)strtoul(argv[2], 0, 0);
+    const int bh = hrr::top_bit(b);
+    const int kp = hrr::bottom_bit(kr);
+    const int kq = hrr::bottom_bit(~kr & ~hrr::low_mask(kp)) - 1;
+    const uint32_t m = kr & hrr::low_mask(bh + 1);
+    printf("%d %d %d %u\n", bh, kp, kq, m);
+    return 0;
+}
+"""
+
+
+def test_section2_bit_example_fixes_fls_and_ffs(tmp_path):
+    """Section 2's worked bit pattern (tests/golden/paper_bit_example.txt):
+    b = 010010 has b_h = 4 and k_r = 100110 has k_p = 1, k_q = 2; the
+    highest / lowest set-bit primitives of the range-minimum code are 0-based
+    and reproduce every printed value, and so does clearing k_r above b_h."""
+    clang = "/opt/rocm/llvm/bin/clang++"
+    if not os.path.exists(clang):
+        pytest.skip("clang++ with __builtin_bitreverse32 is not available")
+    kv = {}
+    with open(os.path.join(ROOT, "tests", "golden", "paper_bit_example.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = line.split()
+                kv[k] = int(v, 0)
+    src = tmp_path / "bits.cpp"
+    src.write_text("#include <cstdlib>\n" + BITS_HARNESS)
+    exe = tmp_path / "bits"
+    subprocess.run([clang, "-O1", "-std=c++17", "-I", CSRC, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe), str(kv["b"]), str(kv["k_r"])], capture_output=True, text=True,
+                         check=True).stdout.split()
+    assert [int(x) for x in out] == [kv["b_h"], kv["k_p"], kv["k_q"], kv["m"]]
+    assert kv["B"] == 6 and kv["b"] < 1 << kv["B"] and kv["k_r"] < 1 << kv["B"]
+
+
 RMQ_HARNESS = r"""
 #include <cstdio>
 #include "hrr_rmq.hpp"

@@ -274,6 +274,61 @@ def test_accept_threshold_reading(orc):
     assert [orc.accept(e, l1, s, x) for x in range(3)] == [True, False, False]
 
 
+def _round_binary32(x):
+    """Round a positive Fraction to the nearest IEEE binary32 value, ties to
+    even (normal range only), with exact rational arithmetic: an independent
+    way to get a correctly rounded reciprocal."""
+    assert x > 0
+    e = x.numerator.bit_length() - x.denominator.bit_length()
+    if Fraction(2) ** e > x:
+        e -= 1
+    assert Fraction(2) ** e <= x < Fraction(2) ** (e + 1)
+    m = x / Fraction(2) ** (e - 23)            # in [2^23, 2^24)
+    n = m.numerator // m.denominator
+    rem = m - n
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    if n == 1 << 24:
+        n, e = 1 << 23, e + 1
+    assert -126 <= e <= 127
+    return float(Fraction(n) * Fraction(2) ** (e - 23))
+
+
+def test_accept_weight_pins(orc):
+    """The roulette weight 1/p of a kept pair (Section 1: a pair survives with
+    probability p and is reweighted by its inverse): exact powers of two,
+    p = 1 for d^2 <= s (weight 1, never above p's clamp), a hand-checked
+    non-representable case, and random pairs against an exact rational
+    reciprocal rounded to binary32 by an independent routine."""
+    e = [0.0, 0.0, 0.0]
+    l1 = [1.0, 0.0, 0.0]
+    for k in range(0, 60):
+        assert orc.accept_weight(e, l1, 2.0 ** -k) == 2.0 ** k
+    # p clamped to 1: d = 0, d^2 = s, d^2 < s
+    assert orc.accept_weight(e, e, 1e-4) == 1.0
+    assert orc.accept_weight(e, [0.25, 0.0, 0.0], 0.0625) == 1.0
+    assert orc.accept_weight(e, [0.25, 0.0, 0.0], 3.0) == 1.0
+    # p = 3/4: 1/p = 4/3 is not a binary32 value; the nearest is 0x3FAAAAAB
+    w = orc.accept_weight(e, l1, 0.75)
+    assert np.float32(w).view(np.uint32) == 0x3FAAAAAB
+    assert _round_binary32(Fraction(4, 3)) == w
+    # random pairs: weight == RN32(1 / p) exactly, p the oracle's own binary32 p
+    rng = np.random.default_rng(41)
+    diffs = 0
+    for _ in range(3000):
+        ev = rng.random(3, dtype=np.float32)
+        lv = rng.random(3, dtype=np.float32)
+        s = float(np.float32(10.0 ** rng.uniform(-7, 0)))
+        p = orc.accept_prob(ev, lv, s)
+        w = orc.accept_weight(ev, lv, s)
+        assert w == _round_binary32(1 / Fraction(p)), (ev, lv, s, p, w)
+        # a reciprocal of the margin-inflated bound would differ
+        infl = float(np.float32(np.float32(p) * np.float32(1.0 + 2.0 ** -20)))
+        if p < 1.0 and _round_binary32(1 / Fraction(infl)) != w:
+            diffs += 1
+    assert diffs > 2500
+
+
 def _single_eye(orc, light, n_l, s, R):
     tile = np.full(4096, R, np.uint32)
     eyes = np.zeros((1, 3), np.float32)
