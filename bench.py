@@ -560,7 +560,8 @@ def main():
     p.add_argument("--epw", type=int, default=0,
                    help="eyes per wave: 0 = the library's choice by hierarchy size (1 for the "
                         "frame's 2^20 lights, 8 for the small case), else 1, 2, 4 or 8")
-    p.add_argument("--stack", type=int, default=512)
+    p.add_argument("--stack", type=int, default=0,
+                   help="LDS stack entries per wave: 0 = the library's choice (192 for one eye per wave)")
     p.add_argument("--traffic-kib", type=float, nargs=2, default=None,
                    metavar=("FETCH", "WRITE"),
                    help="FETCH_SIZE and WRITE_SIZE (KiB per launch) of the traversal kernel "

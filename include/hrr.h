@@ -204,7 +204,7 @@ typedef struct hrr_eyes {
 
 typedef struct hrr_traverse_opts {
     uint32_t eyes_per_wave; /* 0 = tuned or by hierarchy size; else 1, 2, 4 or 8 eyes share one wavefront */
-    uint32_t stack_entries; /* 0 = autotuned; else LDS stack entries per wave, power of two in [256, 4096] */
+    uint32_t stack_entries; /* 0 = autotuned; else LDS stack entries per wave, multiple of 64 in [192, 4096] */
     uint32_t rmq_method;    /* HRR_RMQ_PAPER (default) or one of the HRR_RMQ_* ablations */
     uint32_t n_samples;     /* 0 or 1 = one sample per pair; > 1: Section 3 multi-sample */
     uint32_t psi_s0;        /* start of the golden-ratio lattice psi(n) = s0 + n * alpha mod 1 */
@@ -285,9 +285,9 @@ typedef struct hrr_tune_result {
  * Later launches with eyes_per_wave = 0 or stack_entries = 0 on hierarchies
  * of the same or a neighbouring size class use the remembered choice (the
  * nearest entry); other sizes use the built-in rule.  Candidates are tried
- * in order of preference (fewer eyes per wave first; 512 stack entries, then
- * 256, then 1024) and a later one replaces the best only when it is more than
- * 2 % faster.  The
+ * in order of preference (fewer eyes per wave first; for one eye per wave 192
+ * stack entries, then 256, then 512, otherwise 512, then 256, then 1024) and a
+ * later one replaces the best only when it is more than 2 % faster.  The
  * probe uses at most max_probe_eyes eyes and a scratch output the library
  * allocates.  best (host, optional) receives the winner. */
 hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs, uint32_t n_h,

@@ -101,8 +101,8 @@ void release_scratch(LaunchScratch& S) {
 }
 
 void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes, uint32_t* epw,
-                   uint32_t* cap) {
-    uint32_t e = opts ? opts->eyes_per_wave : 0;
+                   uint32_t* cap, uint32_t fixed_epw) {
+    uint32_t e = fixed_epw ? fixed_epw : (opts ? opts->eyes_per_wave : 0);
     uint32_t c = opts ? opts->stack_entries : 0;
     if (e == 0 || c == 0) {
         TuneVal tv{0, 0, 0, 0.f};
@@ -129,7 +129,8 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
             }
         }
         if (e == 0) e = found ? tv.eyes_per_wave : default_eyes_per_wave(n_lights);
-        if (c == 0) c = found ? tv.stack_entries : 512u;
+        // a tuned stack size only for the shape it was tuned with
+        if (c == 0) c = found && tv.eyes_per_wave == e ? tv.stack_entries : default_stack_entries(e);
     }
     *epw = e;
     *cap = c;
@@ -138,20 +139,20 @@ void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_light
 void group_by_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, const std::vector<HostItem>& items, bool per_item,
                     std::vector<LaunchGroup>& out) {
     out.clear();
-    auto shape_of = [&](const std::vector<size_t>& members, uint32_t* epw, uint32_t* cap) {
+    auto shape_of = [&](const std::vector<size_t>& members, uint32_t* epw, uint32_t* cap, uint32_t fixed_epw) {
         uint64_t max_eyes = 0;
         uint32_t max_lights = 0;
         for (size_t k : members) {
             max_eyes = std::max<uint64_t>(max_eyes, items[k].eyes.n);
             if (items[k].h) max_lights = std::max(max_lights, items[k].h->n_lights);
         }
-        resolve_shape(ctx, opts, max_lights, max_eyes, epw, cap);
+        resolve_shape(ctx, opts, max_lights, max_eyes, epw, cap, fixed_epw);
     };
     if (!per_item) {
         LaunchGroup g;
         g.items.resize(items.size());
         for (size_t k = 0; k < items.size(); ++k) g.items[k] = k;
-        shape_of(g.items, &g.epw, &g.cap);
+        shape_of(g.items, &g.epw, &g.cap, 0);
         out.push_back(std::move(g));
         return;
     }
@@ -167,9 +168,7 @@ void group_by_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, const std::vect
         for (size_t k = 0; k < items.size(); ++k)
             if (item_epw[k] == ge) g.items.push_back(k);
         if (g.items.empty()) continue;
-        uint32_t e_unused = 0;
-        shape_of(g.items, &e_unused, &g.cap);
-        g.epw = ge;
+        shape_of(g.items, &g.epw, &g.cap, ge);
         out.push_back(std::move(g));
     }
 }
@@ -518,7 +517,6 @@ HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs,
     // faster to win, so that probe noise does not trade resident waves for a
     // larger stack (1024 entries halve the waves per SIMD of a full launch)
     static const uint32_t epws[] = {1, 2, 4, 8};
-    static const uint32_t caps[] = {512, 256, 1024};
     TuneVal bestv{0, 0, 0, 1e30f};
     DevBuf out;
     hipEvent_t e0, e1;
@@ -538,7 +536,7 @@ HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs,
         // count pass, then size the scratch output
         uint64_t cnt = 0;
         std::vector<HostItem> items{HostItem{h, probe, s, 0, 0}};
-        hrr_status r = run_sync(ctx, items, nullptr, nullptr, nullptr, &cnt, nullptr, st, 1, 512);
+        hrr_status r = run_sync(ctx, items, nullptr, nullptr, nullptr, &cnt, nullptr, st, 1, default_stack_entries(1));
         if (r != HRR_OK && r != HRR_E_OVERFLOW) {
             result = r;
             break;
@@ -548,7 +546,9 @@ HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs,
             break;
         }
         items[0].out_capacity = cnt;
-        for (uint32_t epw : epws)
+        for (uint32_t epw : epws) {
+            uint32_t caps[3];
+            tune_stack_candidates(epw, caps);
             for (uint32_t cap : caps) {
                 float ms_best = 1e30f;
                 for (int rep = 0; rep < 2; ++rep) {
@@ -568,6 +568,8 @@ HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs,
                 }
                 if (ms_best < bestv.ms * 0.98f) bestv = TuneVal{epw, cap, h->leaf_size, ms_best};
             }
+            if (result != HRR_OK) break;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -125,8 +125,10 @@ inline bool parse_leaf_arg(uint32_t arg, uint32_t* leaf, uint32_t* split) {
 // Resolve launch parameters (eyes per wave, stack entries) from options, the
 // tuner (an entry of the same or a neighbouring light class) and the built-in
 // rule default_eyes_per_wave().
+// With fixed_epw != 0 the eyes per wave are fixed and only the stack size is
+// resolved (a tuned stack size applies only to the shape it was tuned with).
 void resolve_shape(hrr_ctx* ctx, const hrr_traverse_opts* opts, uint32_t n_lights, uint64_t n_eyes,
-                   uint32_t* epw, uint32_t* cap);
+                   uint32_t* epw, uint32_t* cap, uint32_t fixed_epw = 0);
 
 // The launches of a call of several items.  With per_item, the items are
 // grouped by the eyes per wave of their own shape (tuned or by hierarchy

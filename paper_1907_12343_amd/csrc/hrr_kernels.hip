@@ -282,17 +282,43 @@ struct EyeState {
     uint32_t u;     // virtual eye index emitted as the pair's first component
 };
 
-// LDS of one wave: stack ring and eye table.
+// Record fetch of the walk.  One eye per wave: the four lanes of a quad
+// fetch their four 64-byte records as 16-byte quarters, so every load of a
+// quad touches a single record, and the quarters go straight from memory into
+// LDS (global_load_lds_dwordx4 writes lane L's 16 bytes at the instruction's
+// LDS base + 16 L), where each lane reads its own record back.  The area holds
+// one 1040-byte slab per record slot t of a quad: 1024 bytes for the 64 lanes
+// and 16 bytes that stagger the slabs over the LDS banks.  Several eyes per
+// wave (which keep their eyes in LDS and run at lower occupancy): lanes 2i,
+// 2i + 1 fetch both of their records as 32-byte halves and swap halves with a
+// DPP lane exchange.
+constexpr uint32_t kSlab = 1040;
+constexpr uint32_t kXposeBytes = 4 * kSlab;
+template <int EPW>
+struct FetchOf {
+    static constexpr bool quad_lds = EPW == 1;
+};
+
+constexpr uint32_t kEyeTableBytes = 8 * 8 * sizeof(uint32_t);   // 8 words per eye slot
+
+// LDS of one wave: the stack ring, then the eye table (several eyes per wave)
+// or the record area (one eye per wave).
 struct WaveLds {
     uint2* stack;
     uint32_t* eyes;   // 8 words per slot
+    unsigned char* xpose;
 };
 
 // ---- per-wave stack in LDS with spill to device memory ----
 //
-// Logical positions [0, g) live in the wave's spill region, [g, g + n) in the
-// LDS ring at position & (cap - 1).  Only whole halves (cap / 2 entries,
-// aligned) move, so a lane always re-reads exactly what it wrote.
+// Logical positions [0, g) live in the wave's spill region, [g, g + n) in an
+// LDS ring of cap entries (cap a multiple of 64, at least 192); the entry at
+// logical position g sits in ring slot `base`, the next ones follow it round
+// the ring.  Stack memory moves in units of 64 entries, one per lane, so a
+// lane always re-reads exactly what it wrote.  One unit is always enough:
+// after a pop the ring holds at most cap - 64 entries (or none), a step pushes
+// at most 128, so an overflowing push needs at most 64 more slots, and it
+// only overflows when the ring holds more than cap - 128 >= 64 entries.
 //
 // Size bound.  Pops take the top <= 64 entries (lanes in stack order) and
 // each pushes its surviving children next to each other, so depths never
@@ -300,43 +326,42 @@ struct WaveLds {
 // also removes every entry of depth >= d above it; hence all entries of depth
 // d come from one pop and number at most 128, and the stack never holds more
 // than 128 * (max depth + 1) entries.
+constexpr uint32_t kStackUnit = 64;
+
 struct StackState {
-    uint32_t g;   // entries in device memory
-    uint32_t n;   // entries in LDS
+    uint32_t g;      // entries in device memory
+    uint32_t n;      // entries in LDS
+    uint32_t base;   // ring slot of logical position g
     uint32_t max_total;
     uint32_t spills;
 };
 
+// ring slot of x in [0, 2 cap): x or x - cap
+__device__ __forceinline__ uint32_t ring(uint32_t x, uint32_t cap) { return min(x, x - cap); }
+
 __device__ __forceinline__ bool stack_spill(StackState& st, const WaveLds& L, uint2* spill, uint32_t cap,
                                             uint32_t spill_cap, uint32_t* err) {
-    const uint32_t half = cap >> 1;
-    if (st.g + half > spill_cap) {
+    if (st.g + kStackUnit > spill_cap) {
         if (lane_id() == 0) atomicOr(err, (uint32_t)ERR_SPILL_OVERFLOW);
         return false;
     }
     wave_sync();
-    for (uint32_t t = lane_id(); t < half; t += kWave) {
-        const uint32_t pos = st.g + t;
-        spill[pos] = L.stack[pos & (cap - 1)];
-    }
+    spill[st.g + lane_id()] = L.stack[ring(st.base + lane_id(), cap)];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    st.g += half;
-    st.n -= half;
+    st.g += kStackUnit;
+    st.n -= kStackUnit;
+    st.base = ring(st.base + kStackUnit, cap);
     ++st.spills;
     return true;
 }
 
 __device__ __forceinline__ void stack_refill(StackState& st, const WaveLds& L, const uint2* spill, uint32_t cap) {
-    const uint32_t half = cap >> 1;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    const uint32_t base = st.g - half;
-    for (uint32_t t = lane_id(); t < half; t += kWave) {
-        const uint32_t pos = base + t;
-        L.stack[pos & (cap - 1)] = spill[pos];
-    }
+    st.g -= kStackUnit;
+    st.base = ring(st.base + cap - kStackUnit, cap);
+    L.stack[ring(st.base + lane_id(), cap)] = spill[st.g + lane_id()];
     wave_sync();
-    st.g -= half;
-    st.n += half;
+    st.n += kStackUnit;
     ++st.spills;
 }
 
@@ -557,6 +582,7 @@ void traverse_kernel(TravArgs A) {
     WaveLds L;
     L.stack = reinterpret_cast<uint2*>(base);
     L.eyes = reinterpret_cast<uint32_t*>(base + (size_t)cap * sizeof(uint2));
+    L.xpose = base + (size_t)cap * sizeof(uint2);   // one eye per wave: no eye table
     uint2* spill = reinterpret_cast<uint2*>(A.spill) + (size_t)wave_gid * A.spill_cap;
 
     uint64_t st_eyes = 0, st_visits = 0, st_rmq = 0, st_leaf = 0, st_spills = 0;
@@ -629,7 +655,7 @@ void traverse_kernel(TravArgs A) {
         if (STATS) st_eyes += cnt;
 
         StackState S;
-        S.g = 0; S.n = 0; S.max_total = 0; S.spills = 0;
+        S.g = 0; S.n = 0; S.base = 0; S.max_total = 0; S.spills = 0;
 
         // -------- roots --------
         {
@@ -687,10 +713,9 @@ void traverse_kernel(TravArgs A) {
             // they leave early (frame 142.9 -> 142.1 ms)
             __builtin_amdgcn_s_setprio(1);
             const uint32_t n = min(S.n, (uint32_t)kWave);
-            const uint32_t top = S.g + S.n;
             const bool act = lane < n;
             uint2 e = make_uint2(0u, 0u);
-            if (act) e = L.stack[(top - n + lane) & (cap - 1)];
+            if (act) e = L.stack[ring(S.base + S.n - n + lane, cap)];
             S.n -= n;
             wave_sync();
             if (STATS) st_visits += n;
@@ -708,13 +733,40 @@ void traverse_kernel(TravArgs A) {
             uint32_t kL = 0, kR = 0, a = 0, c = 0, b = 0, rightIdx = 0;
             uint32_t mlA = 0, mlN = 0, mrA = 0, mrN = 0;   // multi-light leaf ranges to test
             float wL = 0.0f, wR = 0.0f;
-            // Node records.  Every 16-byte load of a lane that hits its own
-            // cache line costs one vector-L1 tag lookup, and those lookups
-            // bound this loop; so the two lanes of a pair fetch each of their
-            // two records as 32-byte halves (one lookup per pair and load)
-            // and then swap halves with a DPP lane exchange.
+            // Node records.  A load costs about one cycle of the vector-memory
+            // pipeline per distinct cache line that a quad of lanes touches
+            // (more when the line comes from L2 or beyond), so neighbouring
+            // lanes share each record's line (see FetchOf).
             float4 q0, q1, q2, q3;
-            {
+            if (FetchOf<EPW>::quad_lds) {
+                // lane 4g + j fetches quarter j of the records of lanes 4g + t;
+                // quarter j of record t lands at t * kSlab + 64 g + 16 j
+                const uint32_t j = lane & 3u, g4 = lane & ~3u;
+                const uint32_t n0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0x00, 0xF, 0xF, false);
+                const uint32_t n1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0x55, 0xF, 0xF, false);
+                const uint32_t n2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0xAA, 0xF, 0xF, false);
+                const uint32_t n3 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0xFF, 0xF, 0xF, false);
+                typedef __attribute__((address_space(1))) const void* gptr;
+                typedef __attribute__((address_space(3))) void* lptr;
+                unsigned char* xb = L.xpose;
+                if (g4 < n)
+                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n0) + j),
+                                                     (lptr)(xb), 16, 0, 0);
+                if (g4 + 1u < n)
+                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n1) + j),
+                                                     (lptr)(xb + kSlab), 16, 0, 0);
+                if (g4 + 2u < n)
+                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n2) + j),
+                                                     (lptr)(xb + 2 * kSlab), 16, 0, 0);
+                if (g4 + 3u < n)
+                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n3) + j),
+                                                     (lptr)(xb + 3 * kSlab), 16, 0, 0);
+                __builtin_amdgcn_s_setprio(0);
+                wave_sync();
+                const float4* r = reinterpret_cast<const float4*>(xb + j * kSlab + 16u * g4);
+                q0 = r[0]; q1 = r[1]; q2 = r[2]; q3 = r[3];
+                wave_sync();
+            } else {
                 const bool odd = (lane & 1u) != 0u;
                 const uint32_t partner = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, kDppSwapPairs, 0xF, 0xF, false);
                 const uint32_t n_even = odd ? partner : node;   // record of the pair's even lane
@@ -793,10 +845,11 @@ void traverse_kernel(TravArgs A) {
                 if (S.n + npush > cap) {
                     if (!stack_spill(S, L, spill, cap, A.spill_cap, A.error)) break;
                 }
-                const uint32_t at = S.g + S.n + count_below(bl) + count_below(br);
+                // S.n + npush <= cap here, so S.base + at < 2 cap
+                const uint32_t at = S.n + count_below(bl) + count_below(br);
                 const uint32_t tag = (EPW > 1 ? slot : 0u) << kSlotShift;
-                if (pushL) L.stack[at & (cap - 1)] = make_uint2((node + 1u) | tag, kL);
-                if (pushR) L.stack[(at + (pushL ? 1u : 0u)) & (cap - 1)] = make_uint2(rightIdx | tag, kR);
+                if (pushL) L.stack[ring(S.base + at, cap)] = make_uint2((node + 1u) | tag, kL);
+                if (pushR) L.stack[ring(S.base + at + (pushL ? 1u : 0u), cap)] = make_uint2(rightIdx | tag, kR);
                 S.n += npush;
                 wave_sync();
                 const uint32_t tot = S.g + S.n;
@@ -1189,8 +1242,8 @@ hipError_t pick_method(const hrr::TravArgs& A, uint32_t method, bool st, bool w,
 }  // namespace
 
 // LDS bytes of one wave for a given stack size.
-extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap) {
-    return (size_t)stack_cap * sizeof(uint2) + 8 * 8 * sizeof(uint32_t);
+extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap, uint32_t eyes_per_wave) {
+    return (size_t)stack_cap * sizeof(uint2) + (eyes_per_wave > 1 ? hrr::kEyeTableBytes : hrr::kXposeBytes);
 }
 
 // Dynamic LDS bytes of one block.

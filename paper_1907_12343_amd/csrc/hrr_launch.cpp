@@ -13,7 +13,7 @@
 
 extern "C" hipError_t hrr_launch_traverse(const hrr::TravArgs* A, uint32_t eyes_per_wave, uint32_t method,
                                           int stats, int with_weights, uint32_t blocks, hipStream_t stream);
-extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap);
+extern "C" size_t hrr_trav_lds_per_wave(uint32_t stack_cap, uint32_t eyes_per_wave);
 extern "C" size_t hrr_trav_lds_per_block(uint32_t n_items, size_t lds_per_wave);
 extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t method, int stats, int with_weights,
                                              size_t lds_per_block, int* blocks_per_cu);
@@ -27,8 +27,6 @@ extern "C" hipError_t hrr_launch_compact(const hrr::ItemDesc* items, uint32_t n_
 namespace hrr {
 
 namespace {
-
-bool is_pow2(uint32_t x) { return x && !(x & (x - 1)); }
 
 // Bounds of the kernel's product-form keep test for one s (the derivation is
 // beside rr_test in the kernels): t_cull >= s 2^32 (1 + 2^-18) and
@@ -57,14 +55,14 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         return fail(HRR_E_INVALID, "items per launch must be in [1, %u]", kMaxItemsPerLaunch);
     if (!(epw == 1 || epw == 2 || epw == 4 || epw == 8))
         return fail(HRR_E_INVALID, "eyes_per_wave must be 1, 2, 4 or 8");
-    if (!is_pow2(cap) || cap < 256 || cap > 4096)
-        return fail(HRR_E_INVALID, "stack_entries must be a power of two in [256, 4096]");
+    if (cap % 64 != 0 || cap < 192 || cap > 4096)
+        return fail(HRR_E_INVALID, "stack_entries must be a multiple of 64 in [192, 4096]");
     if (method > 5) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
     if (n_samples == 0) n_samples = 1;
     const int with_w = weights != nullptr;
 
     // ---- grid: persistent waves, as many as stay resident ----
-    const size_t lds_wave = hrr_trav_lds_per_wave(cap);
+    const size_t lds_wave = hrr_trav_lds_per_wave(cap, epw);
     const size_t lds_block = hrr_trav_lds_per_block((uint32_t)n, lds_wave);
     int bpc = 0;
     hipError_t e;
@@ -319,9 +317,9 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     }
 
     if (tasks > 0) {
-        const uint32_t half = cap / 2;
+        // 128 entries per tree level (see the kernel's stack), whole 64-entry units, one spare
         const uint64_t bound = 128ull * (dmax + 2);
-        const uint32_t spill_cap = (uint32_t)(((bound + half - 1) / half) * half + half);
+        const uint32_t spill_cap = (uint32_t)(((bound + 63) / 64) * 64 + 64);
         const size_t spill_bytes = (size_t)waves * spill_cap * sizeof(unsigned long long);
         if ((e = S.spill.ensure(spill_bytes)) != hipSuccess) return hip_fail(e, "spill stacks");
 

@@ -79,6 +79,25 @@ inline uint32_t default_eyes_per_wave(uint32_t n_lights) {
     return n_lights >= (1u << 17) ? 1u : n_lights >= (1u << 16) ? 4u : 8u;
 }
 
+// LDS stack entries per wave when neither the caller nor the tuner fixes
+// them.  One eye per wave also keeps a 4160-byte record area in LDS; 192
+// entries (1.5 KB) leave room for 7 waves per SIMD in 160 KB, 256 entries
+// for 6 (frame, power-of-two splits: 123.7 ms at 192 entries against 127.9 ms
+// at 256 and 154.3 ms at 512).  Several eyes per wave run at 96 registers (5
+// waves per SIMD) with their eyes in LDS, where 512 entries cost nothing.
+inline uint32_t default_stack_entries(uint32_t eyes_per_wave) {
+    return eyes_per_wave == 1 ? 192u : 512u;
+}
+
+// Stack sizes the autotuner tries for a shape, in order of preference.
+inline void tune_stack_candidates(uint32_t eyes_per_wave, uint32_t out[3]) {
+    if (eyes_per_wave == 1) {
+        out[0] = 192; out[1] = 256; out[2] = 512;
+    } else {
+        out[0] = 512; out[1] = 256; out[2] = 1024;
+    }
+}
+
 // Output chunk size of an item: about sixteen chunks per wave that touches
 // the item, 2^kMinChunkShift .. 2^kMaxChunkShift pairs.
 inline uint32_t chunk_shift_for(uint64_t capacity, uint64_t touching_waves) {

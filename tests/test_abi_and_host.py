@@ -639,7 +639,7 @@ def test_device_range_minimum_code_on_the_host(orc, rmq_harness):
 LAYOUT_HARNESS = r"""
 #include <cstdio>
 #include "hrr_layout.hpp"
-// stdin lines: "o n virtual_eyes tile_bits" | "q n tasks" | "c capacity waves" | "e n_lights" | "p cost"
+// stdin lines: "o n virtual_eyes tile_bits" | "q n tasks" | "c capacity waves" | "e n_lights" | "p cost" | "s epw"
 int main() {
     char op;
     unsigned long long a, b, c;
@@ -657,6 +657,10 @@ int main() {
             printf("%u\n", hrr::default_eyes_per_wave((uint32_t)a));
         } else if (op == 'p' && scanf("%llu", &a) == 1) {
             printf("%d\n", hrr::order_pays((double)a) ? 1 : 0);
+        } else if (op == 's' && scanf("%llu", &a) == 1) {
+            uint32_t c[3];
+            hrr::tune_stack_candidates((uint32_t)a, c);
+            printf("%u %u %u %u\n", hrr::default_stack_entries((uint32_t)a), c[0], c[1], c[2]);
         } else {
             return 1;
         }
@@ -718,3 +722,10 @@ def test_launch_layout_choices(layout_harness):
     # eye ordering only for launches with enough work: the 4096 x 1024 case (cost 4096 x
     # 1024^0.6 = 262144) goes unordered, 4096 frame eyes x 2^20 lights (16777216) ordered
     assert ask(["p 262144", "p 2097151", "p 2097152", "p 16777216"]) == [(0,), (0,), (1,), (1,)]
+    # stack entries: 192 for one eye per wave (its LDS record area leaves room
+    # for 7 waves per SIMD), 512 otherwise; the default is the first candidate,
+    # every candidate a multiple of 64 in [192, 4096] (the launch's rule)
+    got = ask(["s 1", "s 2", "s 4", "s 8"])
+    assert got == [(192, 192, 256, 512), (512, 512, 256, 1024), (512, 512, 256, 1024), (512, 512, 256, 1024)]
+    for row in got:
+        assert all(c % 64 == 0 and 192 <= c <= 4096 for c in row)

@@ -58,8 +58,10 @@ def test_light_order_matches_oracle(ctx, orc, tiny, tiny_oracle):
 def test_tiny_full_parity(ctx, tiny, tiny_oracle, method, leaf, epw):
     h = ctx.build_hierarchy(tiny["lights"], leaf_size=leaf)
     eyes = _eyes_t(ctx, tiny["eyes"])
+    # one eye per wave on the smallest stack (record area beside it in LDS)
     pairs, n, st = ctx.traverse_all(h, eyes, tiny["s"], tiny["width"], rmq_method=method,
-                                    eyes_per_wave=epw, stack_entries=512, stats=True)
+                                    eyes_per_wave=epw, stack_entries=192 if epw == 1 else 512,
+                                    stats=True)
     got = pair_keys_from_gpu(pairs)
     assert n == tiny_oracle["keys"].size
     assert np.array_equal(got, tiny_oracle["keys"])
@@ -82,17 +84,19 @@ def test_tiny_full_parity_pow2_split(ctx, tiny, tiny_oracle, method, leaf, epw):
     h.free()
 
 
-def test_stack_spills_to_device_memory(ctx, orc):
-    # a wide survivor front (large s) against a 256-entry LDS stack
+@pytest.mark.parametrize("cap,epw", [(192, 1), (256, 1), (320, 1), (192, 4)])
+def test_stack_spills_to_device_memory(ctx, orc, cap, epw):
+    # a wide survivor front (large s) against a small LDS stack ring (any
+    # multiple of 64 entries from 192 on; 64-entry units move to device memory)
     lights = synth.uniform_points(1 << 15, 801)
     eyes = synth.uniform_points(512, 802)
     tile = synth.dither_tile(100)
     s = 2e-2
     h = ctx.build_hierarchy(lights, leaf_size=1)
-    pairs, n, st = ctx.traverse_all(h, _eyes_t(ctx, eyes), s, 64, stack_entries=256,
-                                    eyes_per_wave=1, stats=True)
+    pairs, n, st = ctx.traverse_all(h, _eyes_t(ctx, eyes), s, 64, stack_entries=cap,
+                                    eyes_per_wave=epw, stats=True)
     assert st["spills"] > 0, st
-    assert st["max_stack"] > 256
+    assert st["max_stack"] > cap
     assert st["max_stack"] <= 128 * (h.depth + 1)
     sel = np.arange(0, 512, 5)
     out = orc.accept_eyes(eyes, sel, 64, 0, tile, h.sorted_lights(), s, lists=True)
@@ -362,8 +366,9 @@ def test_invalid_arguments(ctx, tiny):
         ctx.traverse(h, e, 1e-3, 0, capacity=8)
     with pytest.raises(hrr.HrrError):
         ctx.traverse(h, e, 1e-3, 64, capacity=8, eyes_per_wave=3)
-    with pytest.raises(hrr.HrrError):
-        ctx.traverse(h, e, 1e-3, 64, capacity=8, stack_entries=300)
+    for bad_cap in (300, 128, 160, 4160):   # not a multiple of 64 in [192, 4096]
+        with pytest.raises(hrr.HrrError):
+            ctx.traverse(h, e, 1e-3, 64, capacity=8, stack_entries=bad_cap)
     h.free()
 
 
