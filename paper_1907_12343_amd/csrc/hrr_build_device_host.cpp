@@ -65,7 +65,7 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
     uint32_t leaf_size, split;
     if (!parse_leaf_arg(leaf_arg, &leaf_size, &split))
         return fail(HRR_E_INVALID, "leaf_size must be in [1, 8], optionally with HRR_SPLIT_POW2");
-    if (n_lights >= kMaxNodes) return fail(HRR_E_INVALID, "at most %u lights", kMaxNodes - 1);
+    if (n_lights >= kMaxLights) return fail(HRR_E_INVALID, "at most %u lights", kMaxLights - 1);
     float qbox[6] = {0.f, 0.f, 0.f, 1.f, 1.f, 1.f};
     if (box) {
         for (int k = 0; k < 3; ++k)

@@ -46,7 +46,10 @@ namespace hrr {
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+// lanes (of the active ones) whose p holds; the builtin takes the condition as
+// a lane mask directly (the int-valued __ballot materialises it in a register
+// and compares it again)
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // number of set bits of m in lanes below this one
 __device__ __forceinline__ uint32_t count_below(uint64_t m) {
@@ -402,13 +405,19 @@ __device__ __forceinline__ unsigned long long alloc_chunk(const ItemDesc& D) {
 // (frame 144.5 -> 141.9 ms, 256-cache batch 57.2 -> 55.8 ms).
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
+// Stores go through global (address-space 1) pointers: a generic pointer
+// makes them flat stores, which also count against the LDS counter that every
+// stack access of the walk waits on.
+typedef __attribute__((address_space(1))) u32x2 g_u32x2;
+typedef __attribute__((address_space(1))) float g_f32;
+
 __device__ __forceinline__ void put_pair(uint2* p, unsigned long long i, uint2 x) {
     const u32x2 v = {x.x, x.y};
-    __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(p) + i);
+    __builtin_nontemporal_store(v, (g_u32x2*)(p) + i);
 }
 
 __device__ __forceinline__ void put_weight(float* p, unsigned long long i, float w) {
-    __builtin_nontemporal_store(w, p + i);
+    __builtin_nontemporal_store(w, (g_f32*)(p) + i);
 }
 
 // Make `c` the current chunk; direct pointers when the whole chunk lies below
@@ -443,9 +452,12 @@ __device__ __forceinline__ void store_pair(const ItemDesc& D, unsigned long long
     }
 }
 
-// Emit up to two pairs per lane (the first before the second), compacted over
-// the wave (uniform control flow).  A step holds at most 128 pairs and a chunk
-// at least 128, so a step crosses at most one chunk boundary.
+// Emit up to two pairs per lane, compacted over the wave (uniform control
+// flow): every lane's first pair, then every lane's second, so that each of the
+// two store instructions writes one contiguous run.  (With a lane's two pairs
+// side by side, both instructions wrote every cache line in part: 1.52 bytes
+// reached memory per byte of pairs.)  A step holds at most 128 pairs and a
+// chunk at least 128, so a step crosses at most one chunk boundary.
 template <bool W>
 __device__ __forceinline__ void emit2(OutState& O, const ItemDesc& D, bool e0, uint2 p0, float w0, bool e1, uint2 p1,
                                       float w1) {
@@ -462,8 +474,8 @@ __device__ __forceinline__ void emit2(OutState& O, const ItemDesc& D, bool e0, u
     }
     const uint32_t shift = D.chunk_shift;
     const uint32_t C = 1u << shift;
-    const uint32_t pos0 = O.fill + count_below(m0) + count_below(m1);
-    const uint32_t pos1 = pos0 + (e0 ? 1u : 0u);
+    const uint32_t pos0 = O.fill + count_below(m0);
+    const uint32_t pos1 = O.fill + (uint32_t)__popcll(m0) + count_below(m1);
     if (O.wp && O.fill + cnt <= C) {
         if (e0) {
             put_pair(O.wp, pos0, p0);
@@ -583,6 +595,9 @@ void traverse_kernel(TravArgs A) {
     L.stack = reinterpret_cast<uint2*>(base);
     L.eyes = reinterpret_cast<uint32_t*>(base + (size_t)cap * sizeof(uint2));
     L.xpose = base + (size_t)cap * sizeof(uint2);   // one eye per wave: no eye table
+    // the record area's LDS address, wave-uniform (the destination of the
+    // record fetch must be a scalar)
+    const uint32_t xlds = uni((uint32_t)(size_t)(__attribute__((address_space(3))) unsigned char*)L.xpose);
     uint2* spill = reinterpret_cast<uint2*>(A.spill) + (size_t)wave_gid * A.spill_cap;
 
     uint64_t st_eyes = 0, st_visits = 0, st_rmq = 0, st_leaf = 0, st_spills = 0;
@@ -714,7 +729,11 @@ void traverse_kernel(TravArgs A) {
             __builtin_amdgcn_s_setprio(1);
             const uint32_t n = min(S.n, (uint32_t)kWave);
             const bool act = lane < n;
-            uint2 e = make_uint2(0u, 0u);
+            // inactive lanes keep an arbitrary entry: every load and decision
+            // below is masked by `act` (no instruction spent on a default)
+            uint2 e;
+            e.x = __builtin_nondeterministic_value(e.x);
+            e.y = __builtin_nondeterministic_value(e.y);
             if (act) e = L.stack[ring(S.base + S.n - n + lane, cap)];
             S.n -= n;
             wave_sync();
@@ -729,10 +748,14 @@ void traverse_kernel(TravArgs A) {
                 E.R = w[3]; E.kr = w[4]; E.u = w[5];
             }
 
-            bool pushL = false, pushR = false, emitL = false, emitR = false;
-            uint32_t kL = 0, kR = 0, a = 0, c = 0, b = 0, rightIdx = 0;
-            uint32_t mlA = 0, mlN = 0, mrA = 0, mrN = 0;   // multi-light leaf ranges to test
-            float wL = 0.0f, wR = 0.0f;
+            bool pushL = false, pushR = false, emitL = false, emitR = false, multi = false;
+            // read only in lanes whose flags above are set
+            uint32_t kL = __builtin_nondeterministic_value(kL), kR = __builtin_nondeterministic_value(kR);
+            uint32_t a = __builtin_nondeterministic_value(a), c = __builtin_nondeterministic_value(c);
+            uint32_t b = __builtin_nondeterministic_value(b);
+            uint32_t rightIdx = __builtin_nondeterministic_value(rightIdx);
+            float wL = __builtin_nondeterministic_value(wL), wR = __builtin_nondeterministic_value(wR);
+            uint32_t mlN = 0, mrN = 0;   // lights of the multi-light leaves to test (0: none)
             // Node records.  A load costs about one cycle of the vector-memory
             // pipeline per distinct cache line that a quad of lanes touches
             // (more when the line comes from L2 or beyond), so neighbouring
@@ -740,27 +763,26 @@ void traverse_kernel(TravArgs A) {
             float4 q0, q1, q2, q3;
             if (FetchOf<EPW>::quad_lds) {
                 // lane 4g + j fetches quarter j of the records of lanes 4g + t;
-                // quarter j of record t lands at t * kSlab + 64 g + 16 j
+                // quarter j of record t lands at t * kSlab + 64 g + 16 j.
+                // Inactive lanes fetch record 0, so no load needs a lane mask;
+                // byte offsets are 32-bit (records of at most 2^26 nodes), the
+                // base and the LDS destinations are wave-uniform.
                 const uint32_t j = lane & 3u, g4 = lane & ~3u;
-                const uint32_t n0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0x00, 0xF, 0xF, false);
-                const uint32_t n1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0x55, 0xF, 0xF, false);
-                const uint32_t n2 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0xAA, 0xF, 0xF, false);
-                const uint32_t n3 = (uint32_t)__builtin_amdgcn_mov_dpp((int)node, 0xFF, 0xF, 0xF, false);
+                const uint32_t nd = act ? node : 0u;
+                const uint32_t jo = j << 4;
+                const uint32_t o0 = ((uint32_t)__builtin_amdgcn_mov_dpp((int)nd, 0x00, 0xF, 0xF, false) << 6) | jo;
+                const uint32_t o1 = ((uint32_t)__builtin_amdgcn_mov_dpp((int)nd, 0x55, 0xF, 0xF, false) << 6) | jo;
+                const uint32_t o2 = ((uint32_t)__builtin_amdgcn_mov_dpp((int)nd, 0xAA, 0xF, 0xF, false) << 6) | jo;
+                const uint32_t o3 = ((uint32_t)__builtin_amdgcn_mov_dpp((int)nd, 0xFF, 0xF, 0xF, false) << 6) | jo;
+                typedef __attribute__((address_space(1))) const unsigned char* gbytes;
                 typedef __attribute__((address_space(1))) const void* gptr;
                 typedef __attribute__((address_space(3))) void* lptr;
+                const gbytes rec = (gbytes)(D.nodes);
+                __builtin_amdgcn_global_load_lds((gptr)(rec + o0), (lptr)(size_t)(xlds), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((gptr)(rec + o1), (lptr)(size_t)(xlds + kSlab), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((gptr)(rec + o2), (lptr)(size_t)(xlds + 2 * kSlab), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((gptr)(rec + o3), (lptr)(size_t)(xlds + 3 * kSlab), 16, 0, 0);
                 unsigned char* xb = L.xpose;
-                if (g4 < n)
-                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n0) + j),
-                                                     (lptr)(xb), 16, 0, 0);
-                if (g4 + 1u < n)
-                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n1) + j),
-                                                     (lptr)(xb + kSlab), 16, 0, 0);
-                if (g4 + 2u < n)
-                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n2) + j),
-                                                     (lptr)(xb + 2 * kSlab), 16, 0, 0);
-                if (g4 + 3u < n)
-                    __builtin_amdgcn_global_load_lds((gptr)(reinterpret_cast<const float4*>(D.nodes + n3) + j),
-                                                     (lptr)(xb + 3 * kSlab), 16, 0, 0);
                 __builtin_amdgcn_s_setprio(0);
                 wave_sync();
                 const float4* r = reinterpret_cast<const float4*>(xb + j * kSlab + 16u * g4);
@@ -786,7 +808,12 @@ void traverse_kernel(TravArgs A) {
                 q2 = odd ? r2 : e13;
                 q3 = odd ? o13 : r2;
             }
-            if (act) {
+            // Every lane runs the node arithmetic (inactive ones on whatever
+            // their registers hold, with no range-minimum query); only the
+            // decisions are masked by `act`.  A block masked by `act` cost the
+            // moves that merge its results with defaults every step, and spills
+            // (frame 124.6 -> 122.8 ms).
+            {
                 a = __float_as_uint(q0.w);
                 c = __float_as_uint(q1.w);
                 b = __float_as_uint(q2.w);
@@ -795,7 +822,7 @@ void traverse_kernel(TravArgs A) {
                 // the child holding k inherits the minimum; the other one needs a query
                 const bool kLeft = k < c;
                 const uint32_t qa = kLeft ? c : a;
-                const uint32_t qb = kLeft ? b : c;
+                const uint32_t qb = act ? (kLeft ? b : c) : qa;
                 uint32_t kq = qa;
                 if (qb - qa > 1u) {
                     kq = rmq<METHOD>(qa, qb, E.kr);
@@ -804,7 +831,7 @@ void traverse_kernel(TravArgs A) {
                 kL = kLeft ? k : kq;
                 kR = kLeft ? kq : k;
                 if (METHOD == 5) {   // ablation: the inheriting child's minimum is recomputed too
-                    const uint32_t ia = kLeft ? a : c, ib = kLeft ? c : b;
+                    const uint32_t ia = kLeft ? a : c, ib = act ? (kLeft ? c : b) : ia;
                     uint32_t ki = ia;
                     if (ib - ia > 1u) {
                         ki = rmq<METHOD>(ia, ib, E.kr);
@@ -819,12 +846,14 @@ void traverse_kernel(TravArgs A) {
                 const float d2R = box_d2(E.ex, E.ey, E.ez, q2.x, q2.y, q2.z, q3.x, q3.y, q3.z);
                 const uint32_t vL = rotated(kL, E.R), vR = rotated(kR, E.R);
                 bool sL, sR;
-                const bool openL = rr_fast(vL, D, d2L, nL == 1u, sL);
-                const bool openR = rr_fast(vR, D, d2R, nR == 1u, sR);
+                const bool openL = rr_fast(vL, D, d2L, nL == 1u, sL) && act;
+                const bool openR = rr_fast(vR, D, d2R, nR == 1u, sR) && act;
                 if (openL || openR) {   // rare: one shared block for the IEEE decisions
                     if (openL) sL = keeps(vL, accept_p(s, d2L, nL == 1u ? 1.0f : kBoxMargin));
                     if (openR) sR = keeps(vR, accept_p(s, d2R, nR == 1u ? 1.0f : kBoxMargin));
                 }
+                sL = sL && act;
+                sR = sR && act;
                 pushL = sL && !leafL;
                 pushR = sR && !leafR;
                 emitL = sL && nL == 1u;
@@ -833,9 +862,10 @@ void traverse_kernel(TravArgs A) {
                     if (emitL) wL = 1.0f / accept_p(s, d2L, 1.0f);
                     if (emitR) wR = 1.0f / accept_p(s, d2R, 1.0f);
                 }
-                if (sL && leafL && nL > 1u) { mlA = a; mlN = nL; }
-                if (sR && leafR && nR > 1u) { mrA = c; mrN = nR; }
-                if (STATS) st_leaf += (uint64_t)(nL == 1u) + (uint64_t)(nR == 1u);
+                mlN = sL && leafL && nL > 1u ? nL : 0u;
+                mrN = sR && leafR && nR > 1u ? nR : 0u;
+                multi = mlN + mrN > 0u;
+                if (STATS && act) st_leaf += (uint64_t)(nL == 1u) + (uint64_t)(nR == 1u);
             }
 
             // push survivors: a lane's two children stay adjacent, lanes in order
@@ -860,9 +890,9 @@ void traverse_kernel(TravArgs A) {
             emit2<W>(O, D, emitL, make_uint2(E.u, a), wL, emitR, make_uint2(E.u, c), wR);
 
             // multi-light leaves
-            if (ballot(mlN + mrN > 0u)) {
+            if (ballot(multi)) {
                 uint64_t tests = 0;
-                leaf_lights<W>(O, D, E, mlA, mlN, mrA, mrN, tests);
+                leaf_lights<W>(O, D, E, a, mlN, c, mrN, tests);
                 if (STATS) st_leaf += tests;
             }
         }

@@ -104,7 +104,7 @@ HRR_HD uint32_t refine(uint32_t x, int keep, uint32_t a, uint32_t b) {
 // that member.  Every step therefore ends at or above a, and only the bound
 // b is tested; the bits above j are 0u - (2u << j) (none for j = 31).
 HRR_HD uint32_t refine_inside(uint32_t x, int keep, uint32_t b) {
-    uint32_t todo = x & ~low_mask(keep);
+    uint32_t todo = x & ~low_mask(keep);   // keep = 32: nothing to walk
     while (todo) {
         const int j = bottom_bit(todo);
         const uint32_t step = 1u << j;
@@ -263,7 +263,9 @@ HRR_HD uint32_t rmq_direct(uint32_t a, uint32_t b, uint32_t kr) {
 // member test applies; below g every class meets the range, so the highest
 // zero bit of k_r below g wins and Algorithm 3's refinement walks it to its
 // reflected-smallest member.  No class: the range's reflected-smallest index,
-// the one with the most trailing zeros (Algorithm 1's answer).
+// the one with the most trailing zeros (Algorithm 1's answer) -- which is the
+// same walk started from a with no bit held fixed: each step clears the lowest
+// set bit while the result stays below b.
 HRR_HD uint32_t rmq_paper_select(uint32_t a, uint32_t b, uint32_t kr) {
     // Every case is evaluated with selects; only the refinement walk, needed
     // when no single-member class wins, is a (short) loop.
@@ -284,13 +286,16 @@ HRR_HD uint32_t rmq_paper_select(uint32_t a, uint32_t b, uint32_t kr) {
     const bool at_g = !((kr >> g) & 1u) && t_g < len;
     // below g: every zero bit of k_r has a non-empty class; the highest wins
     const uint32_t z = ~kr & low_mask(g);
-    uint32_t k = most_trailing_zeros(a, b - 1u);   // no class: Algorithm 1's answer
-    if (!first && !above && !at_g && z != 0u) {
-        const int i = top_bit(z);
-        // below g the class step 2^(i+1) is at most the range length, so its
-        // smallest member at or above a lies inside [a,b)
-        k = refine_inside(seed_candidate(a, i, kr & low_mask(i)), i + 1, b);
-    }
+    const bool single = first || above || at_g;
+    // the walk: from the class seed (below g the class step 2^(i+1) is at most
+    // the range length, so its smallest member at or above a lies inside
+    // [a,b)), or from a with nothing held fixed (no class); not at all when a
+    // single candidate wins
+    const int i = top_bit(z | 1u);
+    const bool cls = !single && z != 0u;
+    const uint32_t x0 = cls ? seed_candidate(a, i, kr & low_mask(i)) : a;
+    const int keep = single ? 32 : (cls ? i + 1 : 0);
+    uint32_t k = refine_inside(x0, keep, b);
     k = at_g ? a + t_g : k;
     k = above ? a + dlow : k;
     return first ? kr : k;

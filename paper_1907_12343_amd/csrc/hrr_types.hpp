@@ -83,7 +83,7 @@ struct TravArgs {
     const uint32_t* tile;         // 64 x 64 shifts
     unsigned long long* spill;    // per-wave spill stacks (uint2 entries)
     uint32_t spill_cap;           // entries per wave
-    uint32_t stack_cap;           // LDS stack entries per wave (power of two)
+    uint32_t stack_cap;           // LDS stack entries per wave (a multiple of 64, >= 192)
     uint32_t lds_per_wave;        // bytes
     uint32_t interleave_shift;    // ... or, if > 0, chunks q, q + 8, q + 16, ... of 2^shift tasks
     unsigned long long* stats;    // 8 counters or null
@@ -107,6 +107,9 @@ constexpr uint32_t kMinChunkShift = 7;  // a chunk holds >= 128 pairs (one emiss
 constexpr uint32_t kMaxChunkShift = 13;
 constexpr uint32_t kSlotShift = 28;     // stack entry: node | slot << 28
 constexpr uint32_t kMaxNodes = 1u << kSlotShift;
+// Lights per hierarchy: at most 2^26 - 1, so that the node records (64 bytes
+// each) span at most 4 GiB and the walk addresses them with 32-bit offsets.
+constexpr uint32_t kMaxLights = 1u << 26;
 
 enum StatIdx { ST_EYES = 0, ST_PAIRS, ST_VISITS, ST_RMQ, ST_LEAF, ST_SPILLS, ST_MAXSTACK, ST_N };
 
