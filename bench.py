@@ -1,17 +1,29 @@
 """Benchmark of the hierarchical Russian-roulette hot path on one MI355X.
 
-Default workload (one "step" = one pass of the whole hot path over a frame):
-1920x1080 eye vertices against 2^20 light vertices drawn from one seeded
-64-Gaussian mixture (sigma 0.02) in the unit cube, fp32 positions, 64x64
-dither tile, s = 1e-4, Morton hierarchy with leaf size 1 (built once,
-before timing), one persistent launch per step: per-eye shift, rotated
-radical inverse, range minimum per node (the paper's sweep), node bound,
-cull/descend, exact leaf test and pair emission.  Inputs and the output
-buffer are resident in HBM before timing starts.
+Default run (``python bench.py``): every measurement of the hot path, printed
+as ONE JSON line whose headline is the frame:
 
-Prints ONE JSON line.  Metric: eye-vertex traversals per second (the pair
-rate is reported beside it).  Other workloads (--workload rangemin | batched
-| served) are for the design notes, not the headline line.
+* frame (headline; one "step" = one pass of the whole hot path over a frame):
+  1920x1080 eye vertices against 2^20 light vertices drawn from one seeded
+  64-Gaussian mixture (sigma 0.02) in the unit cube, fp32 positions, 64x64
+  dither tile, s = 1e-4, Morton hierarchy with leaf size 1 (built once, before
+  timing), one persistent launch per step: per-eye shift, rotated radical
+  inverse, range minimum per node (the paper's method), node bound,
+  cull/descend, exact leaf test and pair emission.  Inputs and the output
+  buffer are resident in HBM before timing starts.  The headline uses the
+  hierarchy with power-of-two splits; ``frame_other_split`` is the same frame
+  on the radix (highest differing Morton bit) hierarchy;
+* ``range_min``: 2^28 range-minimum queries (a < b uniform u32, uniform shift);
+* ``batched``: 256 caches in one call against 256 plain launches;
+* ``served``: the serving loop at 0.3 / 0.6 / 0.9 of its saturation rate,
+  against plain single launches served one at a time.
+
+``--workload frame|tiny|rangemin|batched|served`` runs one of them alone.
+
+Rooflines price the work with fixed per-unit figures (lane-operations or
+bytes per unit of work, see OPS_* below) times the units the kernel's
+statistics launch counts, divided by the kernel's own duration (HIP events
+around that kernel on the call's stream).
 """
 import argparse
 import json
@@ -27,28 +39,30 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0
 # 32-bit VALU lane-operations: 256 CU x 4 SIMD x 32 lanes x 2.4 GHz = 78.6 T/s,
 # the rate behind the published fp32 vector peak (157.3 TFLOP/s = 78.6 T FMA/s).
-# The traversal's counters show the SIMDs issuing 0.33 wave64 instructions per
-# cycle, which a 16-lane (4-cycle) issue could not reach.
+# (Plain 32-bit integer instructions issue at half that rate on gfx950; the
+# higher denominator is the conservative one.)
 VALU_PEAK_TOPS = 256 * 4 * 32 * 2.4e9 / 1e12
 
-# Algorithmic 32-bit VALU lane-operations per unit of traversal work, counted
-# from the arithmetic each unit needs as gfx950 executes it (the breakdown
-# follows):
-#   visit : one internal node popped, both children bounded -- inherited
-#           minimum selection 5; per child 34 (box distance 9, squares and sum
-#           5, IEEE division 10, margin and min 3, fixed-point keep test 5,
-#           rotated value 2); survivor/leaf decisions 8; ballot compaction 8
-#   rmq   : one range minimum with the default method (case test, bit-parallel
-#           flip-position selection, seed and about two refinement steps)
-#   leaf  : one exact test of a light inside a multi-light leaf
-#   pair  : one emitted pair (compaction, position, store address)
-OPS_VISIT = 5 + 2 * 34 + 8 + 8
-OPS_RMQ = 40
-OPS_LEAF = 30
-OPS_PAIR = 6
+# Algorithmic work per unit (32-bit lane-operations), the hot path's own
+# per-unit figures:
+#   bound : one child's node bound -- box distance, acceptance bound and the
+#           comparison with the child's minimum (~15 fp32/int operations)
+#   rmq   : one range minimum with the paper's sweeps, ~15 sweep steps of ~10
+#           integer operations each on node-like ranges
+#   pair  : one accepted pair: its exact test and its emission (~15)
+#   leaf  : one exact test of a light inside a leaf of several lights (~15)
+#   query : one query of the range-minimum microbenchmark: ~3 sweep steps of
+#           ~10 operations plus ~15 fixed
+OPS_BOUND = 15
+OPS_RMQ = 150
+OPS_PAIR = 15
+OPS_LEAF = 15
+OPS_QUERY = 3 * 10 + 15
 BYTES_PER_QUERY = 20   # range minimum: a, b, r in; argmin, min out
 RMQ_METHODS = {"paper": 0, "direct": 1, "paper_full": 2, "paper_loop": 3, "dyadic": 4,
                "paper_no_reuse": 5}
+# Section 3's extra rotation of sample n: psi(n) = s0 + n alpha (mod 1), s0 fixed here
+PSI_S0 = 0x6A09E667
 
 
 def _sync_all():
@@ -56,12 +70,76 @@ def _sync_all():
     torch.cuda.synchronize()
 
 
-def frame_workload(args):
+def _free_gpu():
+    import gc
+    import torch
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def lane_ops(st, n_pairs):
+    """Algorithmic lane-operations of a traversal from its statistics: each
+    node visit bounds both children."""
+    return (2 * st["node_visits"] * OPS_BOUND + st["rmq_calls"] * OPS_RMQ
+            + n_pairs * OPS_PAIR + st["leaf_tests"] * OPS_LEAF)
+
+
+def alu_roofline(ops, kernel_ms, traffic=None):
+    achieved = ops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tlane-op/s",
+            "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic}
+
+
+def host_cpu():
+    """Threads this process may run on, the machine's CPU count and model."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return max(1, usable), os.cpu_count() or 1, model
+
+
+def timed_launches(fn, steps, warmup):
+    """Run fn warmup + steps times; wall ms per step and GPU ms per step
+    (torch events on the current stream around the timed steps)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    _sync_all()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    _sync_all()
+    return (time.perf_counter() - t0) * 1e3 / steps, e0.elapsed_time(e1) / steps
+
+
+# ---------------------------------------------------------------------------
+# frame
+# ---------------------------------------------------------------------------
+
+def frame_workload(args, split=None, cpu=True, steps=None, warmup=None):
     import numpy as np
     import torch
     import paper_1907_12343_amd as hrr
     import synth
 
+    split = split or args.split
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     tiny = args.workload == "tiny"
     fr = synth.tiny() if tiny else synth.frame()
     ns = 1 if tiny else max(1, args.samples)
@@ -72,14 +150,14 @@ def frame_workload(args):
         fr = dict(fr, eyes=np.ascontiguousarray(fr["eyes"][:rows * fr["width"]]))
     ctx = hrr.Context(fr["tile"], device=0)
     t0 = time.time()
-    h = ctx.build_hierarchy(fr["lights"], leaf_size=fr["leaf"], split=args.split)
+    h = ctx.build_hierarchy(fr["lights"], leaf_size=fr["leaf"], split=split)
     build_s = time.time() - t0
     lights_dev = torch.from_numpy(fr["lights"]).to("cuda:0")
-    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"], split=args.split)   # warm-up
+    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"], split=split)   # warm-up
     hd.free()
     _sync_all()
     t0 = time.perf_counter()
-    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"], split=args.split)
+    hd = ctx.build_hierarchy_device(lights_dev, leaf_size=fr["leaf"], split=split)
     build_dev_s = time.perf_counter() - t0
     hd.free()
     eyes = torch.from_numpy(fr["eyes"]).to("cuda:0")
@@ -94,45 +172,35 @@ def frame_workload(args):
     kw["weights"] = weights
     # one untimed launch with counters on: units of work for the roofline
     st = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, stats=True, **kw)[2]
-    for _ in range(args.warmup):
-        ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, **kw)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     kernel_ms = []
-    _sync_all()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
+
+    def step():
         # timing=True: the library brackets the traversal kernel with HIP
         # events on this same stream
         _, got, stt = ctx.traverse(h, eyes, fr["s"], fr["width"], pairs=pairs, timing=True, **kw)[:3]
         assert got == n
         kernel_ms.append(stt["kernel_ms"])
-    e1.record(stream)
-    _sync_all()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    step_gpu_ms = e0.elapsed_time(e1) / args.steps
-    gpu_ms = sum(kernel_ms) / len(kernel_ms)
 
-    ops = _ops_of(st, n)
-    achieved = ops / (gpu_ms * 1e-3) / 1e12
+    ms, step_gpu_ms = timed_launches(step, steps, warmup)
+    gpu_ms = sum(kernel_ms[warmup:]) / max(len(kernel_ms) - warmup, 1)
+    ops = lane_ops(st, n)
+    traffic = (_traffic_bytes(args, split=split)
+               if (ns == 1 and not args.weights and not tiny and method == 0) else None)
     line = {
         "metric": "eye-vertex traversals/s",
         "value": n_eyes / (ms * 1e-3),
         "unit": "eyes/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32+f32",
         "data": "synthetic",
-        "config": {"workload": _frame_name(ns, args.weights, tiny, args.split),
-                   "n_eyes": n_eyes, "n_lights": int(fr["lights"].shape[0]), "split": args.split,
+        "config": {"workload": _frame_name(ns, args.weights, tiny, split),
+                   "n_eyes": n_eyes, "n_lights": int(fr["lights"].shape[0]), "split": split,
                    "rmq": args.rmq, "parallelism": "1 GPU"},
         "pairs_per_s": n / (ms * 1e-3),
         "accepted_pairs": n,
@@ -140,28 +208,27 @@ def frame_workload(args):
         "step_gpu_ms": step_gpu_ms,
         "hierarchy_build_s": build_s,
         "hierarchy_build_device_s": build_dev_s,
-        "units": {"node_visits": st["node_visits"], "rmq_calls": st["rmq_calls"],
-                  "leaf_tests": st["leaf_tests"], "pairs": n},
+        "units": {"node_visits": st["node_visits"], "child_bounds": 2 * st["node_visits"],
+                  "rmq_calls": st["rmq_calls"], "leaf_tests": st["leaf_tests"], "pairs": n,
+                  "stack_spills": st["spills"], "max_stack": st["max_stack"]},
         "algorithmic_lane_ops": ops,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": _traffic_bytes(args, split=args.split)
-                     if (ns == 1 and not args.weights and not tiny) else None},
+        "roofline": alu_roofline(ops, gpu_ms, traffic),
     }
     if ns > 1:
         line["config"]["samples_per_eye"] = ns
         line["config"]["psi_s0"] = PSI_S0
-    traffic = line["roofline"]["traffic"]
     if traffic is not None:
         # everything that leaves the L2s (Infinity Cache hits included),
-        # beside the ALU roofline: the walk is co-limited by VALU issue and
-        # the vector-memory address path, not by this stream
+        # beside the ALU roofline (from the recorded counter runs)
         line["memory_side"] = {"bytes": traffic, "TB_per_s": traffic / (gpu_ms * 1e-3) / 1e12,
-                               "frac_of_hbm_peak": traffic / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    if not args.no_cpu_baseline:
+                               "frac_of_hbm_peak": traffic / (gpu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "source": "profiles/traverse_frame_traffic.json"}
+    if cpu and not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline_frame(fr, fr["eyes"].shape[0], args, ns)
+    del pairs, weights, eyes, lights_dev
     h.free()
     ctx.close()
+    _free_gpu()
     return line
 
 
@@ -214,21 +281,16 @@ def _frame_name(ns, weights, tiny=False, split="radix"):
     elif ns > 1:
         name = ("frame rows 0..%d (1920x%d eyes) x %d samples per eye x 2^20 lights, "
                 "64-Gaussian mixture sigma 0.02, s=1e-4, leaf 1" % (1080 // ns - 1, 1080 // ns, ns))
-    if split == "pow2":
-        name += ", power-of-two splits"
+    name += ", power-of-two splits" if split == "pow2" else ", radix splits"
     if weights:
         name += ", 1/p weights"
     return name + ", one launch"
 
 
-# Section 3's extra rotation of sample n: psi(n) = s0 + n alpha (mod 1), s0 fixed here
-PSI_S0 = 0x6A09E667
-
-
 def cpu_baseline_frame(fr, n_eyes, args, ns=1):
     import numpy as np
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads, cpu_count, model = host_cpu()
     ls = fr["lights"][oracle.morton_order(fr["lights"])]   # the oracle's own light order
     sel = np.linspace(0, n_eyes - 1, max(1, args.cpu_eyes // ns)).astype(np.uint32)
     t0 = time.perf_counter()
@@ -238,15 +300,21 @@ def cpu_baseline_frame(fr, n_eyes, args, ns=1):
     return {"value": sel.size * ns / dt, "unit": "eyes/s", "cores": threads, "kind": "oracle",
             "sample": "%d eyes%s evenly spaced over the eye set, all-pairs test against all %d "
                       "lights (%.1f s)" % (sel.size, " x %d samples" % ns if ns > 1 else "",
-                                           ls.shape[0], dt)}
+                                           ls.shape[0], dt),
+            "host_cpu_count": cpu_count, "cpu_model": model}
 
 
-def rangemin_workload(args):
-    import numpy as np
+# ---------------------------------------------------------------------------
+# range minimum
+# ---------------------------------------------------------------------------
+
+def rangemin_workload(args, steps=None, warmup=None):
     import torch
     import paper_1907_12343_amd as hrr
     import synth
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     if args.rmq == "paper_no_reuse":
         sys.exit("--rmq paper_no_reuse changes the traversal only; range_min has no parent minimum")
     a, b, r = synth.rangemin_queries()
@@ -256,26 +324,13 @@ def rangemin_workload(args):
     k = torch.empty_like(ta)
     v = torch.empty_like(ta)
     method = RMQ_METHODS[args.rmq]
-    for _ in range(args.warmup):
-        ctx.range_min(ta, tb, tr, method=method, out_k=k, out_v=v)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    _sync_all()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.range_min(ta, tb, tr, method=method, out_k=k, out_v=v)
-    e1.record(stream)
-    _sync_all()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    gpu_ms = e0.elapsed_time(e1) / args.steps
+    ms, gpu_ms = timed_launches(lambda: ctx.range_min(ta, tb, tr, method=method, out_k=k, out_v=v),
+                                steps, warmup)
     nq = a.size
     gbs = nq * BYTES_PER_QUERY / (gpu_ms * 1e-3) / 1e9
     line = {
         "metric": "range-min queries/s", "value": nq / (ms * 1e-3), "unit": "queries/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "rangemin: 2^28 queries, a<b uniform u32, r uniform u32",
@@ -283,13 +338,14 @@ def rangemin_workload(args):
         "kernel_ms": gpu_ms,
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": gbs / HBM_PEAK_GBS, "traffic": _traffic_bytes(args, RMQ_TRAFFIC_FILE)},
-        # the integer work beside it: about OPS_RMQ lane-operations per query
-        "valu": {"lane_ops": nq * OPS_RMQ,
-                 "frac": nq * OPS_RMQ / (gpu_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
+        # the integer work beside it
+        "valu": {"lane_ops": nq * OPS_QUERY, "unit": "Tlane-op/s",
+                 "achieved": nq * OPS_QUERY / (gpu_ms * 1e-3) / 1e12,
+                 "frac": nq * OPS_QUERY / (gpu_ms * 1e-3) / 1e12 / VALU_PEAK_TOPS},
     }
     if not args.no_cpu_baseline:
         import oracle
-        threads = max(1, min(16, os.cpu_count() or 1))
+        threads, cpu_count, model = host_cpu()
         a2, b2, r2 = synth.rangemin_check_queries()
         m = min(args.cpu_queries, a2.size)
         t0 = time.perf_counter()
@@ -298,29 +354,32 @@ def rangemin_workload(args):
         line["cpu_baseline"] = {"value": m / dt, "unit": "queries/s", "cores": threads,
                                 "kind": "oracle",
                                 "sample": "%d queries with b-a <= 2^16 by scanning (%.1f s)"
-                                          % (m, dt)}
+                                          % (m, dt),
+                                "host_cpu_count": cpu_count, "cpu_model": model}
+    del ta, tb, tr, k, v
     ctx.close()
+    _free_gpu()
     return line
 
 
-def _ops_of(st, n_pairs):
-    multi_leaf_tests = max(st["leaf_tests"] - 2 * st["node_visits"], 0)
-    return (st["node_visits"] * OPS_VISIT + st["rmq_calls"] * OPS_RMQ
-            + multi_leaf_tests * OPS_LEAF + n_pairs * OPS_PAIR)
+# ---------------------------------------------------------------------------
+# batched
+# ---------------------------------------------------------------------------
 
-
-def batched_workload(args):
+def batched_workload(args, steps=None, warmup=None):
     """256 independent caches (own mixture, 2^U[10,20] lights, 2^U[10,16]
     eyes, s = 1e-4) in ONE call -- one persistent launch per eyes-per-wave
     group of the items -- against 256 plain launches of the same items on the
-    same GPU.  The launch shape and the leaf size come
-    from the autotuner, run once before timing on the cache with the most
-    estimated work (eyes x lights^0.6)."""
+    same GPU.  The leaf size comes from the autotuner, run once before timing
+    on the cache with the most estimated work (eyes x lights^0.6); every
+    group's own ALU fraction is measured with a call of that group alone."""
     import numpy as np
     import torch
     import paper_1907_12343_amd as hrr
     import synth
 
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     ctx = hrr.Context(synth.dither_tile(100), device=0)
     caches = [synth.batched_cache(c) for c in range(256)]
     sizes = np.array([d["lights"].shape[0] for d in caches])
@@ -347,42 +406,49 @@ def batched_workload(args):
     got, st = ctx.traverse_batched(items, pairs, stats=True)
     assert [int(x) for x in got] == counts
 
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-
-    def timed(fn):
-        for _ in range(args.warmup):
-            fn()
-        _sync_all()
-        t0 = time.perf_counter()
-        e0.record(stream)
-        for _ in range(args.steps):
-            fn()
-        e1.record(stream)
-        _sync_all()
-        return (time.perf_counter() - t0) * 1e3 / args.steps, e0.elapsed_time(e1) / args.steps
-
     kms = []
 
     def batched():
         _, stt = ctx.traverse_batched(items, pairs, timing=True)
         kms.append(stt["kernel_ms"])
 
-    ms, step_gpu_ms = timed(batched)
-    gpu_ms = sum(kms[args.warmup:]) / max(len(kms) - args.warmup, 1)
+    ms, step_gpu_ms = timed_launches(batched, steps, warmup)
+    gpu_ms = sum(kms[warmup:]) / max(len(kms) - warmup, 1)
 
     def plain():
         for k, (h, e, d) in enumerate(zip(hs, eyes, caches)):
             ctx.traverse(h, e, d["s"], d["width"], pairs=pairs[offs[k]:offs[k] + max(counts[k], 1)],
                          capacity=counts[k])
 
-    ms_plain, _ = timed(plain)
-    ops = _ops_of(st, total)
-    achieved = ops / (gpu_ms * 1e-3) / 1e12
+    ms_plain, _ = timed_launches(plain, max(1, steps // 4), 1)
+    ops = lane_ops(st, total)
+
+    # the groups alone (same grouping rule as the call: eyes per wave by light class)
+    groups = {}
+    for k, d in enumerate(caches):
+        nl = d["lights"].shape[0]
+        g = "1 eye/wave (>= 2^17 lights)" if nl >= 1 << 17 else (
+            "4 eyes/wave (2^16..2^17 lights)" if nl >= 1 << 16 else "8 eyes/wave (< 2^16 lights)")
+        groups.setdefault(g, []).append(k)
+    per_group = {}
+    for g, ks in groups.items():
+        sub = [items[k] for k in ks]
+        _, sst = ctx.traverse_batched(sub, pairs, stats=True)
+        gk = []
+
+        def run_sub():
+            _, stt = ctx.traverse_batched(sub, pairs, timing=True)
+            gk.append(stt["kernel_ms"])
+
+        timed_launches(run_sub, steps, warmup)
+        g_ms = sum(gk[warmup:]) / max(len(gk) - warmup, 1)
+        g_pairs = int(sum(counts[k] for k in ks))
+        per_group[g] = {"items": len(ks), "eyes": int(sum(caches[k]["eyes"].shape[0] for k in ks)),
+                        "pairs": g_pairs, "kernel_ms": g_ms,
+                        "alu_frac": alu_roofline(lane_ops(sst, g_pairs), g_ms)["frac"]}
     line = {
         "metric": "eye-vertex traversals/s", "value": n_eyes / (ms * 1e-3), "unit": "eyes/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+f32",
         "data": "synthetic",
         "config": {"workload": "batched: 256 caches, own 64-Gaussian mixture each, 2^U[10,20] "
@@ -394,24 +460,31 @@ def batched_workload(args):
         "step_gpu_ms": step_gpu_ms, "setup_s": setup_s,
         "plain_launches": {"ms_per_step": ms_plain, "eyes_per_s": n_eyes / (ms_plain * 1e-3),
                            "speedup_of_batched": ms_plain / ms},
-        "units": {k: st[k] for k in ("node_visits", "rmq_calls", "leaf_tests")},
+        "units": {"node_visits": st["node_visits"], "child_bounds": 2 * st["node_visits"],
+                  "rmq_calls": st["rmq_calls"], "leaf_tests": st["leaf_tests"], "pairs": total},
         "algorithmic_lane_ops": ops,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "Tlane-op/s", "frac": achieved / VALU_PEAK_TOPS, "traffic": None},
+        "roofline": alu_roofline(ops, gpu_ms),
+        "groups": per_group,
     }
+    del pairs, eyes, pe
     for h in hs:
         h.free()
     ctx.close()
+    _free_gpu()
     return line
 
+
+# ---------------------------------------------------------------------------
+# served
+# ---------------------------------------------------------------------------
 
 def served_workload(args):
     """Serving loop: 16 resident hierarchies of 2^(16+6h/15) lights, requests
     of 2^U[8,18] eyes (each with its own shift offset, s = 1e-4) arriving as
     a Poisson stream at 0.3, 0.6 and 0.9 of the measured saturation rate.
-    Reports latency percentiles per load and compares with plain single
-    launches served one at a time (FIFO queue replayed over the measured
-    per-request service times of the plain path)."""
+    Reports latency percentiles per load, the same at 0.9 with strict FIFO
+    admission, and plain single launches served one at a time (FIFO queue
+    replayed over the measured per-request service times of the plain path)."""
     import threading
     import numpy as np
     import torch
@@ -432,8 +505,10 @@ def served_workload(args):
     def submit(q):
         return ctx.submit(hs[int(base["hier"][q])], req_eyes[q], 64, int(base["offset"][q]), s_val)
 
-    ctx.server_start(hbm_budget_bytes=int(args.budget_gib * (1 << 30)), max_inflight=2,
-                     max_batch_eyes=1 << 20, max_batch_items=64, pairs_per_eye_guess=2000.0)
+    def start(overtake_ms):
+        ctx.server_start(hbm_budget_bytes=int(args.budget_gib * (1 << 30)), max_inflight=2,
+                         max_batch_eyes=1 << 20, max_batch_items=64, pairs_per_eye_guess=2000.0,
+                         overtake_ms=overtake_ms)
 
     def drain(tickets, out):
         for t in tickets:
@@ -443,6 +518,7 @@ def served_workload(args):
             out.append((info["done_s"] - info["submit_s"], n, info["launches"]))
             ctx.release(t)
 
+    start(args.overtake_ms)
     # warm-up and saturation: everything submitted at once
     warm = min(16, n_req)
     res = []
@@ -459,8 +535,7 @@ def served_workload(args):
     def n_at(rate):
         return int(min(n_req, max(100, rate * args.load_seconds)))
 
-    loads = {}
-    for load in (0.3, 0.6, 0.9):
+    def offered(load):
         rate = load * sat_rate
         m = n_at(rate)
         arr = synth.served_requests(n_req, rate)["t"][:m]
@@ -475,23 +550,30 @@ def served_workload(args):
 
         th = threading.Thread(target=waiter)
         th.start()
-        start = time.perf_counter()
+        t_start = time.perf_counter()
         for q in range(m):
-            delay = start + arr[q] - time.perf_counter()
+            delay = t_start + arr[q] - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
             tickets[q] = submit(q)
             ready.release()
         th.join()
-        wall = time.perf_counter() - start
+        wall = time.perf_counter() - t_start
         lat = np.array([r[0] for r in out]) * 1e3
-        loads["%.1f" % load] = {
-            "offered_req_per_s": rate, "requests": m, "p50_ms": float(np.percentile(lat, 50)),
-            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
-            "pairs_per_s": sum(r[1] for r in out) / wall,
-            "eyes_per_s": float(base["size"][:m].sum()) / wall,
-            "retried": int(sum(1 for r in out if r[2] > 1))}
+        return {"offered_req_per_s": rate, "requests": m, "p50_ms": float(np.percentile(lat, 50)),
+                "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+                "pairs_per_s": sum(r[1] for r in out) / wall,
+                "eyes_per_s": float(base["size"][:m].sum()) / wall,
+                "retried": int(sum(1 for r in out if r[2] > 1))}
+
+    loads = {"%.1f" % load: offered(load) for load in (0.3, 0.6, 0.9)}
     stats = ctx.server_stats()
+    ctx.server_stop()
+    # the same 0.9 load with strict FIFO admission (a request that does not
+    # fit holds up everything behind it)
+    start(0.0)
+    drain([submit(q) for q in range(warm)], [])
+    fifo_09 = offered(0.9)
     ctx.server_stop()
 
     # plain single launches: upload, count, traverse, one request at a time
@@ -523,37 +605,76 @@ def served_workload(args):
         "data": "synthetic",
         "config": {"workload": "served: 16 resident hierarchies 2^(16+6h/15) lights, Poisson "
                                "requests of 2^U[8,18] eyes, own shift offset, s=1e-4",
-                   "requests": n_req, "budget_gib": args.budget_gib, "parallelism": "1 GPU"},
+                   "requests": n_req, "budget_gib": args.budget_gib, "split": args.split,
+                   "overtake_ms": args.overtake_ms, "parallelism": "1 GPU"},
         "saturation": {"req_per_s": sat_rate, "eyes_per_s": sat_eyes, "pairs_per_s": sat_pairs},
-        "loads": loads, "plain_single_launches": plain,
+        "loads": loads, "strict_fifo_admission_0.9": fifo_09, "plain_single_launches": plain,
         "server_stats": stats, "setup_s": setup_s, "roofline": None,
     }
     for h in hs:
         h.free()
     ctx.close()
+    _free_gpu()
     return line
+
+
+# ---------------------------------------------------------------------------
+# everything
+# ---------------------------------------------------------------------------
+
+def _brief(line, keys):
+    return {k: line[k] for k in keys if k in line}
+
+
+def all_workloads(args):
+    """The frame as the headline line, and every other measurement beside it."""
+    head = frame_workload(args)
+    other = "radix" if args.split == "pow2" else "pow2"
+    fo = frame_workload(args, split=other, cpu=False, steps=max(3, args.steps // 2),
+                        warmup=min(args.warmup, 3))
+    head["frame_other_split"] = dict(
+        _brief(fo, ("value", "unit", "ms_per_step", "pairs_per_s", "kernel_ms", "units",
+                    "algorithmic_lane_ops", "roofline")),
+        workload=fo["config"]["workload"], split=other)
+    rm = rangemin_workload(args, steps=max(5, args.steps), warmup=max(2, args.warmup))
+    head["range_min"] = dict(_brief(rm, ("value", "unit", "ms_per_step", "kernel_ms", "roofline",
+                                         "valu", "cpu_baseline")),
+                             workload=rm["config"]["workload"])
+    bt = batched_workload(args, steps=max(3, args.steps // 2), warmup=min(args.warmup, 2))
+    head["batched"] = dict(_brief(bt, ("value", "unit", "ms_per_step", "kernel_ms", "pairs_per_s",
+                                       "plain_launches", "units", "algorithmic_lane_ops",
+                                       "roofline", "groups")),
+                           workload=bt["config"]["workload"], leaf=bt["config"]["leaf"])
+    sv = served_workload(args)
+    head["served"] = dict(_brief(sv, ("value", "unit", "saturation", "loads",
+                                      "strict_fifo_admission_0.9", "plain_single_launches")),
+                          workload=sv["config"]["workload"], overtake_ms=args.overtake_ms)
+    return head
 
 
 def main():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=5)
-    p.add_argument("--warmup", type=int, default=2)
-    p.add_argument("--workload", default="frame",
-                   choices=["frame", "tiny", "rangemin", "batched", "served"])
+    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", default="all",
+                   choices=["all", "frame", "tiny", "rangemin", "batched", "served"])
     p.add_argument("--requests", type=int, default=300, help="served: requests per load")
     p.add_argument("--budget-gib", type=float, default=64.0, help="served: device arena")
-    p.add_argument("--load-seconds", type=float, default=10.0,
+    p.add_argument("--load-seconds", type=float, default=8.0,
                    help="served: seconds of arrivals per offered load")
+    p.add_argument("--overtake-ms", type=float, default=100.0,
+                   help="served: a queued request that does not fit is passed over by later "
+                        "ones until it has waited this long (0 = strict FIFO admission)")
     p.add_argument("--rmq", default="paper", choices=list(RMQ_METHODS),
                    help="range-minimum method: paper (bit-parallel flip-position selection, "
                         "default), direct, paper_full (sweeps as loops), paper_loop (pruned loops), "
                         "dyadic (aligned blocks, not the paper's), paper_no_reuse (frame only: "
                         "no inheritance of the parent's argmin)")
     p.add_argument("--split", default="pow2", choices=["radix", "pow2"],
-                   help="hierarchy split rule: pow2 (left child = largest power of two below "
-                        "the length; default, 8 %% faster on the frame) or radix (highest "
-                        "differing Morton bit, the library's default)")
+                   help="hierarchy split rule of the headline (the default run also measures "
+                        "the other): pow2 (left child = largest power of two below the length) "
+                        "or radix (highest differing Morton bit, the library's default)")
     p.add_argument("--samples", type=int, default=1,
                    help="frame: samples per eye (rotation psi(n) per sample; fewer pixel rows)")
     p.add_argument("--weights", action="store_true", help="frame: also write 1/p per pair")
@@ -576,8 +697,9 @@ def main():
         print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the sharded design is documented, not built)", file=sys.stderr)
         sys.exit(2)
-    fn = {"frame": frame_workload, "tiny": frame_workload, "rangemin": rangemin_workload,
-          "batched": batched_workload, "served": served_workload}[args.workload]
+    fn = {"all": all_workloads, "frame": frame_workload, "tiny": frame_workload,
+          "rangemin": rangemin_workload, "batched": batched_workload,
+          "served": served_workload}[args.workload]
     line = fn(args)
     print(json.dumps(line), flush=True)
 

@@ -90,7 +90,20 @@ int hrr_version(void);
 
 /* All methods return the same (argmin, min).  Methods 0-3 differ in how the
  * paper's steps are scheduled on the VALU; method 4 is a different closed form
- * kept for comparison. */
+ * kept for comparison.
+ *
+ * Method 0 follows the paper's case analysis (Section 2: k_r in the range,
+ * an index above the threshold, or none) and its two sweeps, but evaluates
+ * the sweeps' candidate positions with O(1) bit tests instead of visiting
+ * them one by one: both sweeps end at the highest zero bit of k_r whose
+ * prefix class (k_r's bits below it, a 1 at it) meets [a,b) -- positions at
+ * or above k_p, the left-to-right sweep's, outrank the right-to-left sweep's
+ * below it -- and "meets [a,b)" is a closed-form membership test of a residue
+ * class.  What remains a loop is Algorithm 3's walk, which refines the
+ * winning class to its reflected-smallest member (and, with no class,
+ * walks from a to the index with the most trailing zeros, Algorithm 1's
+ * answer).  HRR_RMQ_PAPER_FULL runs the sweeps as printed, one candidate at
+ * a time; all methods return the same result on every query. */
 #define HRR_RMQ_PAPER 0u      /* default: the paper's case analysis and sweeps (Section 2, Algorithms 2
                                  and 3) with all candidate flip positions tested at once in bit
                                  arithmetic, then Algorithm 3's refinement of the winning prefix */
@@ -216,13 +229,19 @@ typedef struct hrr_stats {
     uint64_t pairs;         /* accepted pairs (true count, also past capacity) */
     uint64_t node_visits;   /* internal nodes popped (each tests both children) */
     uint64_t rmq_calls;     /* range minima computed with the paper's method */
-    uint64_t leaf_tests;    /* exact per-light acceptance tests */
+    uint64_t leaf_tests;    /* exact tests of lights inside leaves of several lights (or of a
+                               hierarchy that is a single leaf); a one-light child is decided by
+                               its bound at the parent and is not counted here */
     uint64_t spills;        /* stack chunks moved between LDS and device memory */
     uint64_t max_stack;     /* deepest stack seen by any wave */
     double kernel_ms;       /* traversal kernel duration with HRR_F_TIMING, else 0 */
 } hrr_stats;
 
-/* Hierarchical Russian roulette of every eye of `eyes` against `h`.
+/* Hierarchical Russian roulette of every eye of `eyes` against `h`
+ * (Section 1: each eye vertex draws one rotated radical-inverse number per
+ * light, a pair survives with probability p, and the light hierarchy is
+ * walked top-down, a node being culled when the minimum of the eye's numbers
+ * over the node's index range already fails the node's acceptance bound).
  *
  * Output: the accepted pairs as u32 (j, i) in pairs_out (device,
  * 2*capacity u32), i the sequence index (see hrr_hierarchy_permutation), in
@@ -252,7 +271,8 @@ typedef struct hrr_work_item {
 } hrr_work_item;
 
 /* Many independent (hierarchy, eye set) items in one persistent launch fed by
- * a device work queue.  With opts->eyes_per_wave = 0 each item's shape is
+ * a device work queue; every item is the culling of hrr_traverse (Section 1,
+ * as above) for its own eyes and hierarchy.  With opts->eyes_per_wave = 0 each item's shape is
  * resolved on its own (tuned entry of its light class or a neighbouring one,
  * else 8 eyes per wave below 2^16 lights, 4 below 2^17, then 1) and the call
  * enqueues one such launch per group of equal shape on `stream`, largest

@@ -865,7 +865,6 @@ void traverse_kernel(TravArgs A) {
                 mlN = sL && leafL && nL > 1u ? nL : 0u;
                 mrN = sR && leafR && nR > 1u ? nR : 0u;
                 multi = mlN + mrN > 0u;
-                if (STATS && act) st_leaf += (uint64_t)(nL == 1u) + (uint64_t)(nR == 1u);
             }
 
             // push survivors: a lane's two children stay adjacent, lanes in order

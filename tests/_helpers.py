@@ -52,3 +52,32 @@ def per_eye_counts(pairs_t, n_eyes, chunk=1 << 27):
         u = pairs_t[s:s + chunk, 0].to(torch.int64) & M32
         cnt += torch.bincount(u, minlength=n_eyes)
     return cnt.cpu().numpy()
+
+
+def _mix64(x):
+    """A SplitMix64-style finaliser on int64 tensors (wrapping arithmetic)."""
+    x = x ^ (x >> 30)
+    x = x * -4658895280553007687      # 0xBF58476D1CE4E5B9 as a signed 64-bit value
+    x = x ^ (x >> 27)
+    x = x * -7723592293110705685      # 0x94D049BB133111EB
+    return x ^ (x >> 31)
+
+
+def per_eye_fingerprints(pairs_t, n_eyes, chunk=1 << 27):
+    """Per-eye (count, sum of h1(i), sum of h2(i)) of a possibly huge (n, 2)
+    pair tensor, in wrapping 64-bit arithmetic; two sets of pairs with equal
+    fingerprints for every eye are equal unless two independent 64-bit sums
+    collide."""
+    import torch
+    dev = pairs_t.device
+    cnt = torch.zeros(n_eyes, dtype=torch.int64, device=dev)
+    s1 = torch.zeros(n_eyes, dtype=torch.int64, device=dev)
+    s2 = torch.zeros(n_eyes, dtype=torch.int64, device=dev)
+    for s in range(0, pairs_t.shape[0], chunk):
+        blk = pairs_t[s:s + chunk]
+        u = blk[:, 0].to(torch.int64) & M32
+        i = blk[:, 1].to(torch.int64) & M32
+        cnt.index_add_(0, u, torch.ones_like(u))
+        s1.index_add_(0, u, _mix64(i))
+        s2.index_add_(0, u, _mix64(i ^ 0x5DEECE66D))
+    return cnt.cpu().numpy(), s1.cpu().numpy(), s2.cpu().numpy()

@@ -10,7 +10,8 @@ import numpy as np
 import pytest
 
 import synth
-from _helpers import pair_keys_from_gpu, pair_keys_from_oracle, select_pairs_of_eyes
+from _helpers import (pair_keys_from_gpu, pair_keys_from_oracle, per_eye_fingerprints,
+                      select_pairs_of_eyes)
 
 pytestmark = pytest.mark.gpu
 
@@ -389,6 +390,65 @@ def test_served_requests_equal_plain_and_oracle(ctx, orc):
         ctx.server_stop()
     for sc in scenes:
         sc["h"].free()
+
+
+def test_served_at_the_served_configs_sizes(ctx, orc):
+    """Requests of 2^16..2^18 eyes against hierarchies of the served workload's
+    largest sizes (2^20.8, 2^21.2 and 2^22 lights, power-of-two splits, the
+    benchmark's build) mixed with small ones, served together: every result
+    equals the plain launch of the same request (one eye per wave for the
+    large hierarchies, several for the small ones, each group with its own
+    stack size) and sampled eyes equal the oracle."""
+    import torch
+    big = [12, 13, 15]                       # synth.served_hierarchy(h): 2^(16 + 6h/15) lights
+    scenes = []
+    for h in big:
+        sc = synth.served_hierarchy(h)
+        scenes.append(dict(lights=sc["lights"], centers=sc["centers"],
+                           h=ctx.build_hierarchy(sc["lights"], split="pow2")))
+    assert scenes[-1]["h"].n_lights == 1 << 22
+    small = _served_setup(ctx, sizes=(1 << 12, 1 << 15))
+    scenes += small
+    rng = np.random.default_rng(777)
+    reqs = []
+    for q, (k, lg) in enumerate([(0, 16.0), (1, 17.0), (2, 18.0), (2, 16.5), (1, 17.5),
+                                 (3, 10.0), (4, 12.0), (3, 11.0)]):
+        n = int(np.floor(2.0 ** lg))
+        eyes = synth.request_eyes(scenes[k]["centers"], n, int(rng.integers(1 << 31)))
+        reqs.append(dict(scene=k, eyes=eyes, offset=int(rng.integers(0, 1 << 32)), width=64, s=1e-4))
+    ctx.server_start(hbm_budget_bytes=64 << 30, max_inflight=2, max_batch_items=16,
+                     max_batch_eyes=1 << 20, pairs_per_eye_guess=2000.0)
+    try:
+        tickets = [ctx.submit(scenes[r["scene"]]["h"], r["eyes"], r["width"], r["offset"], r["s"])
+                   for r in reqs]
+        for t in tickets:
+            assert ctx.wait(t, 120000)
+        for q, (t, r) in enumerate(zip(tickets, reqs)):
+            sc = scenes[r["scene"]]
+            res = ctx.result(t)
+            ne = r["eyes"].shape[0]
+            # billions of pairs: compared by per-eye count and two 64-bit hash sums
+            got = per_eye_fingerprints(res, ne)
+            plain, n_plain, _ = ctx.traverse_all(sc["h"], _dev(ctx, r["eyes"]), r["s"], r["width"],
+                                                 shift_offset=r["offset"])
+            want = per_eye_fingerprints(plain, ne)
+            assert res.shape[0] == n_plain or (n_plain == 0 and res.shape[0] == 1), "request %d" % q
+            for a_, b_ in zip(got, want):
+                assert np.array_equal(a_, b_), "request %d" % q
+            del plain
+            torch.cuda.empty_cache()
+            sel = np.sort(rng.choice(r["eyes"].shape[0], 6, replace=False)).astype(np.uint32)
+            o = _oracle_keys(orc, sc["lights"], r["eyes"], sel, r["width"], r["offset"], r["s"])
+            assert np.array_equal(select_pairs_of_eyes(res, sel), o), "request %d" % q
+            del res
+            ctx.release(t)
+        st = ctx.server_stats()
+        assert st["completed"] == len(reqs)
+    finally:
+        ctx.server_stop()
+    for sc in scenes:
+        sc["h"].free()
+    torch.cuda.empty_cache()
 
 
 def test_served_overflow_is_retried_exactly(ctx):

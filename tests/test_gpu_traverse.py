@@ -438,6 +438,74 @@ def test_frame_scale_sampled_pow2_split(ctx, orc):
     hp.free()
 
 
+def test_frame_scale_multi_sample_sampled(ctx, orc):
+    """Section 3's several samples per eye at the benchmark's shape (the first
+    270 pixel rows x 4 samples, about one frame of virtual eyes, power-of-two
+    hierarchy): sampled eyes, all four samples each, pair for pair against
+    the oracle."""
+    import torch
+    ns, s0 = 4, 0x6A09E667
+    fr = synth.frame()
+    rows = 1080 // ns
+    eyes_np = np.ascontiguousarray(fr["eyes"][:rows * fr["width"]])
+    h = ctx.build_hierarchy(fr["lights"], leaf_size=1, split="pow2")
+    perm = orc.morton_order(fr["lights"])
+    eyes = _eyes_t(ctx, eyes_np)
+    n = ctx.count(h, eyes, fr["s"], fr["width"], n_samples=ns, psi_s0=s0)
+    pairs, n1, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n, n_samples=ns, psi_s0=s0)
+    assert n1 == n
+    n_eyes = eyes_np.shape[0]
+    sel = np.unique(np.concatenate([np.arange(3, n_eyes, 2039), [n_eyes - 1]])).astype(np.uint32)
+    out = orc.accept_eyes(eyes_np, sel, fr["width"], 0, fr["tile"], fr["lights"][perm], fr["s"],
+                          n_samples=ns, psi_s0=s0, lists=True)
+    virt = (sel.astype(np.int64)[:, None] * ns + np.arange(ns)[None, :]).ravel()
+    assert np.array_equal(select_pairs_of_eyes(pairs, virt), pair_keys_from_oracle(out, sel, ns))
+    del pairs
+    torch.cuda.empty_cache()
+    h.free()
+
+
+def test_frame_scale_weights_sampled(ctx, orc):
+    """The frame with 1/p weights (power-of-two hierarchy, the benchmark's
+    --weights run): sampled eyes pair for pair against the oracle, and the
+    weight of every pair of those eyes bit for bit against the oracle's
+    correctly rounded reciprocal."""
+    import torch
+    fr = synth.frame()
+    h = ctx.build_hierarchy(fr["lights"], leaf_size=1, split="pow2")
+    perm = orc.morton_order(fr["lights"])
+    ls = fr["lights"][perm]
+    eyes = _eyes_t(ctx, fr["eyes"])
+    n_eyes = fr["eyes"].shape[0]
+    n = ctx.count(h, eyes, fr["s"], fr["width"])
+    pairs, n1, _, w = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n, with_weights=True)
+    assert n1 == n
+    sel = np.unique(np.concatenate([np.arange(11, n_eyes, 8209), [n_eyes - 1]])).astype(np.uint32)
+    out = orc.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], ls, fr["s"], lists=True)
+    # the selected eyes' pairs with their weights, from the huge output in chunks
+    sel_t = torch.as_tensor(sel.astype(np.int64), device=pairs.device)
+    keys, wts = [], []
+    for at in range(0, n, 1 << 27):
+        pc = pairs[at:at + (1 << 27)].to(torch.int64) & 0xFFFFFFFF
+        m = torch.isin(pc[:, 0], sel_t)
+        if m.any():
+            keys.append((pc[m, 0] << 32) | pc[m, 1])
+            wts.append(w[at:at + (1 << 27)][m])
+        del pc, m
+    k = torch.cat(keys)
+    order = torch.argsort(k)
+    k = k[order].cpu().numpy().view(np.uint64)
+    wv = torch.cat(wts)[order].cpu().numpy()
+    assert np.array_equal(k, pair_keys_from_oracle(out, sel))
+    j = (k >> np.uint64(32)).astype(np.int64)
+    i = (k & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    for q in range(k.size):
+        assert np.float32(wv[q]) == np.float32(orc.accept_weight(fr["eyes"][j[q]], ls[i[q]], fr["s"])), q
+    del pairs, w
+    torch.cuda.empty_cache()
+    h.free()
+
+
 def test_frame_scale_sampled(ctx, orc):
     """1920x1080 eyes against 2^20 Gaussian-mixture lights in one launch (the
     benchmark shape); sampled eyes compared pair for pair with the oracle, and
