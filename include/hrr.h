@@ -259,6 +259,33 @@ hrr_status hrr_traverse(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes* ey
                         float* weights_out, uint64_t capacity, uint64_t* n_pairs,
                         hrr_stats* stats, void* stream);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): hrr_traverse of one
+ * eye set with nothing allocated and nothing read back.  Every buffer the
+ * launch needs beyond the caller's inputs and outputs comes from one fixed
+ * 128 MiB scratch array per GPU, which the library holds for the life of the
+ * process; the call only enqueues kernels on `stream` (no memset, no copy, no
+ * host synchronization) and returns.
+ *   result_dev (device, 2 u64): after the stream reaches the end of the call,
+ *     result_dev[0] = the true number of accepted pairs and result_dev[1] = 0,
+ *     or a non-zero internal error code (the scratch is sized so that it
+ *     should never be).
+ *   pairs_out / weights_out / capacity: as hrr_traverse (the first
+ *     min(count, capacity) positions hold distinct accepted pairs, all of
+ *     them when count <= capacity; the overflow is visible as
+ *     result_dev[0] > capacity).
+ *   opts: as hrr_traverse; HRR_F_STATS and HRR_F_TIMING are rejected
+ *     (HRR_E_INVALID), and eyes are processed in index order.
+ * The grid is cut to as many whole blocks as the scratch holds: with the
+ * stack spill area sized for the hierarchy's depth, about 23 KB per wave at
+ * depth 20; a hierarchy too deep for one block returns HRR_E_INVALID.
+ * Output chunks hold at most 1024 pairs.  All calls on one GPU share its
+ * scratch: calls that overlap in time on one GPU (several streams, several
+ * threads) race and must be serialised by the caller. */
+hrr_status hrr_traverse_noalloc(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes* eyes, float s,
+                                const hrr_traverse_opts* opts, uint32_t* pairs_out, float* weights_out,
+                                uint64_t capacity, unsigned long long* result_dev, void* stream);
+
 /* One unit of a batched launch: an eye set against one hierarchy, with its
  * own slice [out_offset, out_offset + out_capacity) of the output buffers. */
 typedef struct hrr_work_item {

@@ -108,6 +108,7 @@ SIGNATURES = {
     "hrr_free_hierarchy": (None, [_P, _P]),
     "hrr_traverse": (_i32, [_P, _P, _P, _f32, _P, _P, _P, _u64, _P, _P, _P]),
     "hrr_traverse_batched": (_i32, [_P, _P, _u32, _P, _P, _P, _P, _P, _P]),
+    "hrr_traverse_noalloc": (_i32, [_P, _P, _P, _f32, _P, _P, _P, _u64, _P, _P]),
     "hrr_autotune": (_i32, [_P, _P, _u32, _P, _f32, _u32, _P, _P]),
     "hrr_tuned_leaf_size": (_u32, [_P, _u32]),
     "hrr_server_start": (_i32, [_P, _P]),
@@ -365,6 +366,20 @@ class Context:
         if weights is not None:
             return out + (weights[:k],)
         return out
+
+    def traverse_noalloc(self, h: Hierarchy, eyes, s: float, width: int, pairs, result,
+                         weights=None, shift_offset: int = 0, pixel_base: int = 0,
+                         capacity: Optional[int] = None, stream=None, **opt):
+        """Enqueue the allocation-free traversal (nothing allocated, nothing
+        read back).  pairs: (capacity, 2) int32 device tensor; result: int64
+        device tensor of 2 elements that receives (true count, status)."""
+        E = self._eyes(eyes, width, shift_offset, pixel_base)
+        o = _opts(**opt)
+        capacity = pairs.shape[0] if capacity is None else min(capacity, pairs.shape[0])
+        _check(_lib.hrr_traverse_noalloc(self.handle, h.handle, ctypes.byref(E), float(s),
+                                         ctypes.byref(o), _dptr(pairs), _dptr(weights), capacity,
+                                         _dptr(result), _stream_handle(stream)),
+               "hrr_traverse_noalloc")
 
     def traverse_all(self, h: Hierarchy, eyes, s, width, **kw):
         """traverse() after a count-only pass that sizes the output exactly."""

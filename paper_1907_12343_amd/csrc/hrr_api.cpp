@@ -15,6 +15,8 @@
 #include "hrr_ctx.hpp"
 #include "hrr_layout.hpp"
 
+extern "C" hipError_t hrr_noalloc_scratch(int device, void** out);   // hrr_kernels.hip
+
 #define HRR_EXPORT extern "C" __attribute__((visibility("default")))
 
 // kernels (hrr_kernels.hip)
@@ -230,6 +232,13 @@ HRR_EXPORT hrr_status hrr_create(int device, const uint32_t* tile, hrr_ctx** out
         (void)hipFree(c->d_tile);
         delete c;
         return hip_fail(e, "tile upload");
+    }
+    // this device's scratch of the allocation-free traversal (its address is
+    // looked up once per device, with the device current)
+    if ((e = hrr_noalloc_scratch(device, &c->noalloc_scratch)) != hipSuccess) {
+        (void)hipFree(c->d_tile);
+        delete c;
+        return hip_fail(e, "scratch address of the allocation-free traversal");
     }
     // Common trailing zeros and significant bits of the tile's values: the
     // eye ordering groups eyes by the low significant bits of their shift.
@@ -487,6 +496,15 @@ HRR_EXPORT hrr_status hrr_traverse(hrr_ctx* ctx, const hrr_hierarchy* h, const h
     hrr_status st = run_sync(ctx, items, opts, pairs_out, weights_out, &count, stats, (hipStream_t)stream);
     if (st == HRR_OK || st == HRR_E_OVERFLOW) *n_pairs = count;
     return st;
+}
+
+HRR_EXPORT hrr_status hrr_traverse_noalloc(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes* eyes, float s,
+                                           const hrr_traverse_opts* opts, uint32_t* pairs_out,
+                                           float* weights_out, uint64_t capacity,
+                                           unsigned long long* result_dev, void* stream) {
+    if (!ctx || !h || !eyes || !result_dev) return fail(HRR_E_INVALID, "hrr_traverse_noalloc: null argument");
+    return launch_noalloc(ctx, h, *eyes, s, opts, pairs_out, weights_out, capacity, result_dev,
+                          (hipStream_t)stream);
 }
 
 HRR_EXPORT hrr_status hrr_traverse_batched(hrr_ctx* ctx, const hrr_work_item* items, uint32_t n_items,

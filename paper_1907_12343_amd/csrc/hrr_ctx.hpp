@@ -104,6 +104,7 @@ struct hrr_ctx {
     std::map<int, uint32_t> tune_leaf;   // log2 lights -> leaf size
     hrr::Server* server = nullptr;
     std::mutex server_mu;
+    void* noalloc_scratch = nullptr;   // this device's scratch of hrr_traverse_noalloc
 };
 
 namespace hrr {
@@ -157,5 +158,11 @@ double timed_kernel_ms(LaunchScratch& S);
 hrr_status finish_items(hrr_ctx* ctx, LaunchScratch& S);
 
 void release_scratch(LaunchScratch& S);
+
+// The allocation-free traversal of one eye set (hrr_traverse_noalloc): every
+// launch on `stream`, nothing allocated, nothing read back.
+hrr_status launch_noalloc(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes& eyes, float s,
+                          const hrr_traverse_opts* opts, uint32_t* pairs, float* weights, uint64_t capacity,
+                          unsigned long long* result_dev, hipStream_t stream);
 
 }  // namespace hrr

@@ -32,6 +32,8 @@
 // a one-light leaf's test is bit-identical to the all-pairs definition.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "hrr_compact.hpp"
 #include "hrr_rmq.hpp"
 #include "hrr_types.hpp"
@@ -1184,7 +1186,75 @@ __global__ __launch_bounds__(256) void compact_move_kernel(const ItemDesc* __res
     }
 }
 
+// ---------------------------------------------------------------------------
+// the allocation-free traversal: set-up and result kernels
+// ---------------------------------------------------------------------------
+
+// Writes the launch's item and task tables into the scratch header and
+// clears its queue heads, counters and status words (a kernel, not a memset
+// or a copy, so that the call records only kernel launches).
+__global__ __launch_bounds__(256) void noalloc_setup_kernel(ItemDesc D, uint32_t n_tasks, unsigned char* base) {
+    uint32_t* q = reinterpret_cast<uint32_t*>(base + kNoAllocQueues);
+    for (uint32_t t = threadIdx.x; t < kQueues * kQueueStride; t += blockDim.x) q[t] = 0u;
+    unsigned long long* c = reinterpret_cast<unsigned long long*>(base + kNoAllocCounters);
+    for (uint32_t t = threadIdx.x; t < CNT_STRIDE; t += blockDim.x) c[t] = 0ull;
+    unsigned long long* m = reinterpret_cast<unsigned long long*>(base + kNoAllocMisc);
+    for (uint32_t t = threadIdx.x; t < 16u; t += blockDim.x) m[t] = 0ull;
+    if (threadIdx.x == 0) {
+        *reinterpret_cast<ItemDesc*>(base + kNoAllocItem) = D;
+        uint32_t* tb = reinterpret_cast<uint32_t*>(base + kNoAllocTasks);
+        tb[0] = 0u;
+        tb[1] = n_tasks;
+    }
+}
+
+// result[0] = the item's true pair count, result[1] = the status word (0 when
+// the launch and its compaction completed).
+__global__ void noalloc_finish_kernel(const unsigned char* base, unsigned long long* result) {
+    if (threadIdx.x == 0) {
+        result[0] = reinterpret_cast<const unsigned long long*>(base + kNoAllocCounters)[CNT_PAIRS];
+        result[1] = reinterpret_cast<const unsigned long long*>(base + kNoAllocMisc)[1] & 0xFFFFFFFFull;
+    }
+}
+
 }  // namespace hrr
+
+// Scratch of the allocation-free traversal.  Every GPU the library runs on
+// holds its own copy for the life of the process; host code reaches it only
+// through the per-device address below (the array's name is not a device
+// address in host code).
+static __device__ __align__(256) unsigned char scratch[hrr::kNoAllocScratchBytes];
+
+// Device address of this GPU's scratch, looked up once per device with that
+// device current (called by hrr_create) and kept.
+extern "C" hipError_t hrr_noalloc_scratch(int device, void** out) {
+    static std::mutex mu;
+    static void* addr[64] = {};
+    if (device < 0 || device >= 64 || !out) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[device] = p;
+    }
+    *out = addr[device];
+    return hipSuccess;
+}
+
+extern "C" hipError_t hrr_launch_noalloc_setup(const hrr::ItemDesc* D, uint32_t n_tasks, void* base,
+                                               hipStream_t stream) {
+    hipLaunchKernelGGL(hrr::noalloc_setup_kernel, dim3(1), dim3(256), 0, stream, *D, n_tasks,
+                       static_cast<unsigned char*>(base));
+    return hipGetLastError();
+}
+
+extern "C" hipError_t hrr_launch_noalloc_finish(const void* base, unsigned long long* result, hipStream_t stream) {
+    hipLaunchKernelGGL(hrr::noalloc_finish_kernel, dim3(1), dim3(64), 0, stream,
+                       static_cast<const unsigned char*>(base), result);
+    return hipGetLastError();
+}
 
 // ---------------------------------------------------------------------------
 // launchers (called from the C++ runtime)

@@ -23,6 +23,9 @@ extern "C" hipError_t hrr_launch_order(const hrr::OrderItem* items, const uint32
                                        hipStream_t stream);
 extern "C" hipError_t hrr_launch_compact(const hrr::ItemDesc* items, uint32_t n_items, uint32_t* error,
                                          hipStream_t stream);
+extern "C" hipError_t hrr_launch_noalloc_setup(const hrr::ItemDesc* D, uint32_t n_tasks, void* base,
+                                               hipStream_t stream);
+extern "C" hipError_t hrr_launch_noalloc_finish(const void* base, unsigned long long* result, hipStream_t stream);
 
 namespace hrr {
 
@@ -364,6 +367,148 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
     if ((e = hipMemcpyAsync(S.h_pinned + n * CNT_STRIDE, d_misc + 1, (1 + ST_N) * sizeof(unsigned long long),
                             hipMemcpyDeviceToHost, stream)) != hipSuccess)
         return hip_fail(e, "read status");
+    return HRR_OK;
+}
+
+// The allocation-free traversal.  Same kernels as launch_items for one item,
+// with every buffer the launch needs carved out of the device's fixed scratch
+// (kNoAllocScratchBytes): the header, then per wave a stack spill region
+// sized for the hierarchy's depth (the walk's bound, 128 entries per level),
+// then the partial-chunk list and compaction plan (one entry per wave: a
+// one-item launch leaves its item once per wave), then the output slack (two
+// chunks per wave).  The grid is the resident one, cut to as many whole
+// blocks as the scratch holds; output chunks have at most 2^10 pairs.  Eyes
+// run in index order (the result does not depend on the order).
+hrr_status launch_noalloc(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes& eyes, float s,
+                          const hrr_traverse_opts* opts, uint32_t* pairs, float* weights, uint64_t capacity,
+                          unsigned long long* result_dev, hipStream_t stream) {
+    if (h->owner != ctx) return fail(HRR_E_INVALID, "hrr_traverse_noalloc: hierarchy belongs to another context");
+    if (!ctx->noalloc_scratch) return fail(HRR_E_DEVICE, "hrr_traverse_noalloc: no scratch on this device");
+    if (!(s > 0.0f) || !isfinite(s)) return fail(HRR_E_INVALID, "hrr_traverse_noalloc: s must be finite and > 0");
+    if (eyes.n > 0 && !eyes.xyz) return fail(HRR_E_INVALID, "hrr_traverse_noalloc: null eye positions");
+    if (eyes.width == 0) return fail(HRR_E_INVALID, "hrr_traverse_noalloc: width must be >= 1");
+    if (capacity > 0 && !pairs) return fail(HRR_E_INVALID, "hrr_traverse_noalloc: null pairs buffer");
+    const uint32_t flags = opts ? opts->flags : 0u;
+    if (flags & (HRR_F_STATS | HRR_F_TIMING))
+        return fail(HRR_E_INVALID, "hrr_traverse_noalloc: statistics and timing need a readback; not supported");
+    const uint32_t method = opts ? opts->rmq_method : HRR_RMQ_PAPER;
+    if (method > 5) return fail(HRR_E_INVALID, "unknown rmq method %u", method);
+    const uint32_t n_samples = opts && opts->n_samples > 1 ? opts->n_samples : 1u;
+    const uint64_t nv = (uint64_t)eyes.n * n_samples;
+    if (nv > 0xFFFFFFFFull) return fail(HRR_E_INVALID, "hrr_traverse_noalloc: eyes x samples exceeds 2^32 - 1");
+    uint32_t epw = 1, cap = 192;
+    resolve_shape(ctx, opts, h->n_lights, eyes.n, &epw, &cap);
+    if (!(epw == 1 || epw == 2 || epw == 4 || epw == 8))
+        return fail(HRR_E_INVALID, "eyes_per_wave must be 1, 2, 4 or 8");
+    if (cap % 64 != 0 || cap < 192 || cap > 4096)
+        return fail(HRR_E_INVALID, "stack_entries must be a multiple of 64 in [192, 4096]");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const int with_w = weights != nullptr;
+    const size_t lds_wave = hrr_trav_lds_per_wave(cap, epw);
+    const size_t lds_block = hrr_trav_lds_per_block(1, lds_wave);
+    int bpc = 0;
+    if ((e = hrr_traverse_occupancy(epw, method, 0, with_w, lds_block, &bpc)) != hipSuccess)
+        return hip_fail(e, "occupancy");
+    if (bpc <= 0) return fail(HRR_E_INVALID, "stack of %u entries does not fit in LDS", cap);
+    const uint64_t tasks = h->n_lights ? (nv + epw - 1) / epw : 0;
+
+    // ---- scratch layout: as many whole blocks as the scratch holds ----
+    const uint64_t spill_cap = (128ull * (h->depth + 2) + 63) / 64 * 64 + 64;    // entries per wave
+    const uint64_t pair_bytes = 8ull + (with_w ? 4ull : 0ull);
+    const uint64_t resident = std::max<uint64_t>(1, (uint64_t)ctx->n_cu * bpc) * kWavesPerBlock;
+    const uint64_t needed = std::max<uint64_t>(kWavesPerBlock, (tasks + kWavesPerBlock - 1) / kWavesPerBlock * kWavesPerBlock);
+    uint64_t waves = std::min(resident, needed);
+    uint32_t shift = std::min<uint32_t>(chunk_shift_for(capacity, std::min<uint64_t>(waves, std::max<uint64_t>(tasks, 1))),
+                                        kNoAllocMaxChunkShift);
+    auto bytes_for = [&](uint64_t w, uint32_t sh) {
+        return kNoAllocHeaderBytes + w * spill_cap * 8ull + w * 2ull * 8ull + (3ull * w + 4ull) * 8ull +
+               (capacity ? 2ull * w * (1ull << sh) * pair_bytes : 0ull) + 1024ull;
+    };
+    while (waves > kWavesPerBlock && bytes_for(waves, shift) > kNoAllocScratchBytes)
+        waves -= kWavesPerBlock;
+    if (bytes_for(waves, shift) > kNoAllocScratchBytes)
+        return fail(HRR_E_INVALID, "hrr_traverse_noalloc: a hierarchy of depth %u needs more than the "
+                    "%llu-byte scratch for one block", h->depth, (unsigned long long)kNoAllocScratchBytes);
+    const uint32_t blocks = (uint32_t)(waves / kWavesPerBlock);
+    unsigned char* base = static_cast<unsigned char*>(ctx->noalloc_scratch);
+    uint64_t at = kNoAllocHeaderBytes;
+    auto carve = [&](uint64_t bytes) {
+        unsigned char* p = base + at;
+        at += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    const uint64_t pk = std::max<uint64_t>(1, std::min<uint64_t>(waves, tasks));
+    uint2* spill = reinterpret_cast<uint2*>(carve(waves * spill_cap * 8ull));
+    unsigned long long* partials = reinterpret_cast<unsigned long long*>(carve(pk * 2ull * 8ull));
+    unsigned long long* plan = reinterpret_cast<unsigned long long*>(carve((3ull * pk + 4ull) * 8ull));
+    const unsigned long long slack = capacity ? 2ull * pk << shift : 0ull;
+    uint32_t* slack_pairs = reinterpret_cast<uint32_t*>(carve(std::max<unsigned long long>(slack, 1) * 8ull));
+    float* slack_weights = with_w ? reinterpret_cast<float*>(carve(std::max<unsigned long long>(slack, 1) * 4ull)) : nullptr;
+    if (at > kNoAllocScratchBytes) return fail(HRR_E_DEVICE, "hrr_traverse_noalloc: scratch layout exceeds its size");
+
+    ItemDesc D;
+    memset(&D, 0, sizeof D);
+    D.nodes = h->d_nodes;
+    D.lights = h->d_lights;
+    D.eyes = eyes.xyz;
+    D.pairs = pairs;
+    D.weights = weights;
+    D.slack_pairs = slack_pairs;
+    D.slack_weights = slack_weights;
+    D.order = nullptr;
+    D.counters = reinterpret_cast<unsigned long long*>(base + kNoAllocCounters);
+    D.partials = partials;
+    D.plan = plan;
+    D.capacity = capacity;
+    D.slack = slack;
+    D.partial_cap = (uint32_t)pk;
+    D.chunk_shift = shift;
+    D.n_lights = h->n_lights;
+    D.n_nodes = h->n_nodes;
+    D.leaf_size = h->leaf_size;
+    D.n_virtual = h->n_lights ? (uint32_t)nv : 0u;
+    D.width = eyes.width;
+    D.shift_offset = eyes.shift_offset;
+    D.pixel_base = eyes.pixel_base;
+    D.n_samples = n_samples;
+    D.psi_s0 = opts ? opts->psi_s0 : 0u;
+    D.s = s;
+    product_test_bounds(s, &D.t_cull, &D.t_keep, &D.d2_fast);
+    for (int q = 0; q < 3; ++q) {
+        D.root_lo[q] = h->box[q];
+        D.root_hi[q] = h->box[3 + q];
+    }
+    D.task_begin = 0;
+
+    if ((e = hrr_launch_noalloc_setup(&D, (uint32_t)tasks, base, stream)) != hipSuccess)
+        return hip_fail(e, "allocation-free set-up");
+    const ItemDesc* d_item = reinterpret_cast<const ItemDesc*>(base + kNoAllocItem);
+    uint32_t* error = reinterpret_cast<uint32_t*>(base + kNoAllocMisc + 8);
+    if (tasks > 0) {
+        TravArgs A;
+        memset(&A, 0, sizeof A);
+        A.items = d_item;
+        A.task_begin = reinterpret_cast<const uint32_t*>(base + kNoAllocTasks);
+        A.n_items = 1;
+        A.n_tasks = (uint32_t)tasks;
+        for (uint32_t q = 0; q <= kQueues; ++q) A.queue_begin[q] = (uint32_t)(tasks * q / kQueues);
+        A.interleave_shift = 0;
+        A.queues = reinterpret_cast<uint32_t*>(base + kNoAllocQueues);
+        A.tile = ctx->d_tile;
+        A.spill = reinterpret_cast<unsigned long long*>(spill);
+        A.spill_cap = (uint32_t)spill_cap;
+        A.stack_cap = cap;
+        A.lds_per_wave = (uint32_t)lds_wave;
+        A.stats = nullptr;
+        A.error = error;
+        if ((e = hrr_launch_traverse(&A, epw, method, 0, with_w, blocks, stream)) != hipSuccess)
+            return hip_fail(e, "allocation-free traverse launch");
+        if (capacity > 0 && (e = hrr_launch_compact(d_item, 1, error, stream)) != hipSuccess)
+            return hip_fail(e, "allocation-free output compaction");
+    }
+    if ((e = hrr_launch_noalloc_finish(base, result_dev, stream)) != hipSuccess)
+        return hip_fail(e, "allocation-free result");
     return HRR_OK;
 }
 

@@ -111,9 +111,25 @@ constexpr uint32_t kMaxNodes = 1u << kSlotShift;
 // each) span at most 4 GiB and the walk addresses them with 32-bit offsets.
 constexpr uint32_t kMaxLights = 1u << 26;
 
+// Scratch of the allocation-free traversal (hrr_traverse_noalloc): one
+// device array per GPU, 128 MiB, laid out as a header (queue heads, counters,
+// status words, the item and task tables), then per-wave stack spill regions,
+// the partial-chunk list, the compaction plan and the output slack.
+constexpr unsigned long long kNoAllocScratchBytes = 128ull << 20;
+constexpr unsigned long long kNoAllocHeaderBytes = 4096;
+constexpr unsigned long long kNoAllocQueues = 0;        // kQueues * kQueueStride u32
+constexpr unsigned long long kNoAllocCounters = 1024;   // CNT_STRIDE u64
+constexpr unsigned long long kNoAllocMisc = 1152;       // 16 u64: [1] = error word
+constexpr unsigned long long kNoAllocItem = 1280;       // one ItemDesc
+constexpr unsigned long long kNoAllocTasks = 1792;      // task table {0, n_tasks}
+constexpr uint32_t kNoAllocMaxChunkShift = 10;          // output chunks of at most 1024 pairs
+
 enum StatIdx { ST_EYES = 0, ST_PAIRS, ST_VISITS, ST_RMQ, ST_LEAF, ST_SPILLS, ST_MAXSTACK, ST_N };
 
 // Kernel-reported (1, 2) and host-detected (4) internal failures.
 enum ErrCode { ERR_NONE = 0, ERR_SPILL_OVERFLOW = 1, ERR_PARTIALS_OVERFLOW = 2, ERR_UNFILLED = 4 };
+
+static_assert(sizeof(ItemDesc) <= kNoAllocTasks - kNoAllocItem, "item table slot");
+static_assert(kQueues * kQueueStride * sizeof(uint32_t) <= kNoAllocCounters, "queue heads slot");
 
 }  // namespace hrr
