@@ -10,7 +10,7 @@
 //
 // Steps (all stream-ordered; the host reads back one count per level):
 //   1. codes   : 63-bit Morton code per light (21-bit cells, x highest)
-//   2. sort    : stable LSD radix sort of (code, index) pairs (hipCUB)
+//   2. sort    : stable LSD radix sort of (code, index) pairs, 8-bit digits
 //   3. gather  : lights in sequence order as float4, codes in sequence order
 //   4. levels  : breadth-first, one launch per level: split every internal
 //                node of the level, append its internal children to the next
@@ -22,10 +22,12 @@
 //                right = self + 1 + internal nodes of the left subtree) and
 //                the 64-byte records at those numbers
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "hrr_devbuild.hpp"
+#include "hrr_scan.hpp"
 #include "hrr_types.hpp"
 
 namespace hrr {
@@ -224,6 +226,109 @@ __global__ void init_root_kernel(Bfs T, uint32_t n) {
     }
 }
 
+
+// ---- stable LSD radix sort of (code, index) pairs ----------------------
+//
+// Eight passes of 8-bit digits cover the 63 code bits, least significant
+// digit first.  One pass is three steps: the digit counts of every tile of
+// kSortTile keys, an exclusive scan of those counts laid out digit-major
+// (digit d of tile b at d * n_tiles + b, so the scan hands every (digit,
+// tile) pair the first output position of its keys), and a scatter that
+// ranks each tile's keys stably.  A tile is read in kSortRounds rounds of
+// 256 consecutive keys; a key's rank is its digit's next free position in the
+// tile, plus the keys of its round with the same digit in earlier waves, plus
+// those in earlier lanes of its own wave (found with eight ballots, one per
+// digit bit).  Keys of one digit therefore leave in index order, which makes
+// every pass stable and the result ordered by (code, original index).
+
+constexpr uint32_t kSortThreads = 256;
+constexpr uint32_t kSortRounds = 16;
+constexpr uint32_t kSortTile = kSortThreads * kSortRounds;
+constexpr uint32_t kSortDigits = 256;
+constexpr uint32_t kSortPasses = 8;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Lanes of the wave (among `valid`) whose digit equals this lane's.
+__device__ __forceinline__ uint64_t same_digit_lanes(uint32_t d, uint64_t valid) {
+    uint64_t peers = valid;
+#pragma unroll
+    for (uint32_t bit = 0; bit < 8u; ++bit) {
+        const bool set = (d >> bit) & 1u;
+        const uint64_t m = __builtin_amdgcn_ballot_w64(set);
+        peers &= set ? m : ~m;
+    }
+    return peers;
+}
+
+__global__ __launch_bounds__(kSortThreads) void sort_count_kernel(const uint64_t* __restrict__ key, uint32_t n,
+                                                                  uint32_t shift, uint32_t n_tiles,
+                                                                  uint32_t* __restrict__ counts) {
+    __shared__ uint32_t hist[kSortDigits];
+    const uint32_t t = threadIdx.x;
+    hist[t] = 0u;
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kSortTile;
+    for (uint32_t r = 0; r < kSortRounds; ++r) {
+        const uint32_t i = base + r * kSortThreads + t;
+        const bool ok = i < n;
+        const uint32_t d = ok ? (uint32_t)(key[i] >> shift) & (kSortDigits - 1u) : 0u;
+        const uint64_t peers = same_digit_lanes(d, __builtin_amdgcn_ballot_w64(ok));
+        if (ok && lanes_below(peers) == 0u) atomicAdd(&hist[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    counts[(size_t)t * n_tiles + blockIdx.x] = hist[t];
+}
+
+__global__ __launch_bounds__(kSortThreads) void sort_scatter_kernel(const uint64_t* __restrict__ kin,
+                                                                    const uint32_t* __restrict__ vin, uint32_t n,
+                                                                    uint32_t shift, uint32_t n_tiles,
+                                                                    const uint32_t* __restrict__ first,
+                                                                    uint64_t* __restrict__ kout,
+                                                                    uint32_t* __restrict__ vout) {
+    // next[d]: the tile's next output position for digit d (thread d owns it).
+    // pos[r & 1][w][d]: keys of digit d in wave w of round r, then the first
+    // position of those keys; the other parity is cleared for the next round.
+    __shared__ uint32_t next[kSortDigits];
+    __shared__ uint32_t pos[2][kSortThreads / 64][kSortDigits];
+    const uint32_t t = threadIdx.x, w = t >> 6;
+    next[t] = first[(size_t)t * n_tiles + blockIdx.x];
+    for (uint32_t q = 0; q < kSortThreads / 64; ++q) {
+        pos[0][q][t] = 0u;
+        pos[1][q][t] = 0u;
+    }
+    __syncthreads();
+    const uint32_t base = blockIdx.x * kSortTile;
+    for (uint32_t r = 0; r < kSortRounds; ++r) {
+        const uint32_t p = r & 1u;
+        const uint32_t i = base + r * kSortThreads + t;
+        const bool ok = i < n;
+        const uint64_t k = ok ? kin[i] : 0ull;
+        const uint32_t v = ok ? vin[i] : 0u;
+        const uint32_t d = (uint32_t)(k >> shift) & (kSortDigits - 1u);
+        const uint64_t peers = same_digit_lanes(d, __builtin_amdgcn_ballot_w64(ok));
+        const uint32_t below = lanes_below(peers);
+        if (ok && below == 0u) pos[p][w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        uint32_t run = next[t];
+        for (uint32_t q = 0; q < kSortThreads / 64; ++q) {
+            const uint32_t c = pos[p][q][t];
+            pos[p][q][t] = run;
+            run += c;
+            pos[p ^ 1u][q][t] = 0u;
+        }
+        next[t] = run;
+        __syncthreads();
+        if (ok) {
+            const uint32_t at = pos[p][w][d] + below;
+            kout[at] = k;
+            vout[at] = v;
+        }
+    }
+}
+
 }  // namespace devbuild
 }  // namespace hrr
 
@@ -252,16 +357,60 @@ extern "C" hipError_t hrr_dev_codes(const float* xyz, uint32_t n, const float* q
     return hipGetLastError();
 }
 
-// Radix sort of (code, index); temp == nullptr queries temp_bytes.
+size_t align256(size_t b) { return (b + 255u) & ~(size_t)255u; }
+
+// Stable radix sort of (code, index) by code (63 low bits); temp == nullptr
+// queries temp_bytes.  Scratch: a second key and index buffer (the passes
+// alternate between it and the outputs, the last pass landing in the
+// outputs), the per-tile digit counts and the scan's chunk sums.
 extern "C" hipError_t hrr_dev_sort(void* temp, size_t* temp_bytes, const uint64_t* code_in, uint64_t* code_out,
                                    const uint32_t* idx_in, uint32_t* idx_out, uint32_t n, hipStream_t stream) {
-    return hipcub::DeviceRadixSort::SortPairs(temp, *temp_bytes, code_in, code_out, idx_in, idx_out, (int)n, 0, 63,
-                                              stream);
+    static_assert(kSortPasses % 2 == 0, "the last pass must write the outputs");
+    if (!temp_bytes) return hipErrorInvalidValue;
+    const uint32_t n_tiles = (n + kSortTile - 1u) / kSortTile;
+    const uint32_t n_counts = n_tiles * kSortDigits;
+    const size_t b_keys = align256((size_t)n * 8u), b_idx = align256((size_t)n * 4u);
+    const size_t b_counts = align256((size_t)n_counts * 4u), b_sums = align256((size_t)scan::chunk_count(n_counts) * 4u);
+    const size_t need = std::max<size_t>(b_keys + b_idx + b_counts + b_sums, 256u);
+    if (!temp) {
+        *temp_bytes = need;
+        return hipSuccess;
+    }
+    if (*temp_bytes < need) return hipErrorInvalidValue;
+    if (n == 0) return hipSuccess;
+    unsigned char* tp = static_cast<unsigned char*>(temp);
+    uint64_t* k_tmp = reinterpret_cast<uint64_t*>(tp);
+    uint32_t* v_tmp = reinterpret_cast<uint32_t*>(tp + b_keys);
+    uint32_t* counts = reinterpret_cast<uint32_t*>(tp + b_keys + b_idx);
+    uint32_t* sums = reinterpret_cast<uint32_t*>(tp + b_keys + b_idx + b_counts);
+    const uint64_t* ks = code_in;
+    const uint32_t* vs = idx_in;
+    for (uint32_t pass = 0; pass < kSortPasses; ++pass) {
+        uint64_t* kd = (pass & 1u) ? code_out : k_tmp;
+        uint32_t* vd = (pass & 1u) ? idx_out : v_tmp;
+        const uint32_t shift = 8u * pass;
+        sort_count_kernel<<<n_tiles, kSortThreads, 0, stream>>>(ks, n, shift, n_tiles, counts);
+        hipError_t e = scan::exclusive_sum(counts, counts, n_counts, sums, stream);
+        if (e != hipSuccess) return e;
+        sort_scatter_kernel<<<n_tiles, kSortThreads, 0, stream>>>(ks, vs, n, shift, n_tiles, counts, kd, vd);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        ks = kd;
+        vs = vd;
+    }
+    return hipSuccess;
 }
 
+// out[i] = in[0] + ... + in[i - 1]; temp == nullptr queries temp_bytes.
 extern "C" hipError_t hrr_dev_exclusive_sum(void* temp, size_t* temp_bytes, const uint32_t* in, uint32_t* out,
                                             uint32_t n, hipStream_t stream) {
-    return hipcub::DeviceScan::ExclusiveSum(temp, *temp_bytes, in, out, (int)n, stream);
+    if (!temp_bytes) return hipErrorInvalidValue;
+    const size_t need = std::max<size_t>(align256((size_t)scan::chunk_count(n) * 4u), 256u);
+    if (!temp) {
+        *temp_bytes = need;
+        return hipSuccess;
+    }
+    if (*temp_bytes < need) return hipErrorInvalidValue;
+    return scan::exclusive_sum(in, out, n, static_cast<uint32_t*>(temp), stream);
 }
 
 extern "C" hipError_t hrr_dev_gather(const float* xyz, const uint32_t* perm, uint32_t n, float4* lights,

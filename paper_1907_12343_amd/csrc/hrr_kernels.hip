@@ -36,6 +36,7 @@
 
 #include "hrr_compact.hpp"
 #include "hrr_rmq.hpp"
+#include "hrr_scan.hpp"
 #include "hrr_types.hpp"
 
 #pragma clang fp contract(off)
@@ -988,69 +989,6 @@ __global__ __launch_bounds__(256) void order_keys_kernel(const OrderItem* __rest
     }
 }
 
-// Exclusive prefix sum of n counts in place, in three launches: every block
-// sums a chunk of kScanChunk counts, one block scans the chunk sums, and every
-// block rescans its chunk from its base.
-constexpr uint32_t kScanChunk = 4096;   // 16 counts per thread of 256
-constexpr uint32_t kScanMaxChunks = 1024;
-
-// Inclusive scan of one value per thread over a block of 256 (LDS, in order).
-__device__ __forceinline__ uint32_t block_inclusive_scan_256(uint32_t x, uint32_t* lds) {
-    const uint32_t t = threadIdx.x;
-    lds[t] = x;
-    __syncthreads();
-    for (uint32_t off = 1; off < 256u; off <<= 1) {
-        const uint32_t add = t >= off ? lds[t - off] : 0u;
-        __syncthreads();
-        lds[t] += add;
-        __syncthreads();
-    }
-    const uint32_t r = lds[t];
-    __syncthreads();
-    return r;
-}
-
-__global__ __launch_bounds__(256) void scan_chunk_sums_kernel(const uint32_t* __restrict__ v, uint32_t n,
-                                                              uint32_t* __restrict__ sums) {
-    __shared__ uint32_t lds[256];
-    const uint32_t b = blockIdx.x * kScanChunk + threadIdx.x * 16u;
-    uint32_t sum = 0;
-    for (uint32_t q = 0; q < 16u; ++q) sum += b + q < n ? v[b + q] : 0u;
-    const uint32_t incl = block_inclusive_scan_256(sum, lds);
-    if (threadIdx.x == 255u) sums[blockIdx.x] = incl;
-}
-
-__global__ __launch_bounds__(256) void scan_sums_kernel(uint32_t* __restrict__ sums, uint32_t n_chunks) {
-    __shared__ uint32_t lds[256];
-    const uint32_t b = threadIdx.x * 4u;
-    uint32_t x[4], sum = 0;
-    for (uint32_t q = 0; q < 4u; ++q) {
-        x[q] = b + q < n_chunks ? sums[b + q] : 0u;
-        sum += x[q];
-    }
-    uint32_t run = block_inclusive_scan_256(sum, lds) - sum;
-    for (uint32_t q = 0; q < 4u; ++q) {
-        if (b + q < n_chunks) sums[b + q] = run;
-        run += x[q];
-    }
-}
-
-__global__ __launch_bounds__(256) void scan_apply_kernel(uint32_t* __restrict__ v, uint32_t n,
-                                                         const uint32_t* __restrict__ sums) {
-    __shared__ uint32_t lds[256];
-    const uint32_t b = blockIdx.x * kScanChunk + threadIdx.x * 16u;
-    uint32_t x[16], sum = 0;
-    for (uint32_t q = 0; q < 16u; ++q) {
-        x[q] = b + q < n ? v[b + q] : 0u;
-        sum += x[q];
-    }
-    uint32_t run = sums[blockIdx.x] + block_inclusive_scan_256(sum, lds) - sum;
-    for (uint32_t q = 0; q < 16u; ++q) {
-        if (b + q < n) v[b + q] = run;
-        run += x[q];
-    }
-}
-
 __global__ __launch_bounds__(256) void order_scatter_kernel(const uint32_t* __restrict__ keys,
                                                             const uint32_t* __restrict__ vbegin, uint32_t total,
                                                             uint32_t key_bits, uint32_t* __restrict__ offsets,
@@ -1398,8 +1336,7 @@ extern "C" hipError_t hrr_launch_order(const hrr::OrderItem* items, const uint32
     if (rbits > 31u || (rbits && tile_tz > 31u)) return hipErrorInvalidValue;
     const uint32_t key_bits = 3u * bits + rbits;
     const uint32_t n_buckets = n_items << key_bits;
-    const uint32_t n_chunks = (n_buckets + hrr::kScanChunk - 1u) / hrr::kScanChunk;
-    if (n_chunks > hrr::kScanMaxChunks) return hipErrorInvalidValue;
+    if (hrr::scan::chunk_count(n_buckets) > 1024u) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(hist, 0, (size_t)n_buckets * sizeof(uint32_t), stream);
     if (e != hipSuccess) return e;
     uint32_t blocks = (total + 255u) / 256u;
@@ -1407,10 +1344,7 @@ extern "C" hipError_t hrr_launch_order(const hrr::OrderItem* items, const uint32
     if (blocks > max_blocks) blocks = max_blocks;
     hipLaunchKernelGGL(hrr::order_keys_kernel, dim3(blocks), dim3(256), 0, stream, items, vbegin, n_items, total, bits,
                        rbits, tile, tile_tz, keys, hist);
-    uint32_t* sums = hist + n_buckets;
-    hipLaunchKernelGGL(hrr::scan_chunk_sums_kernel, dim3(n_chunks), dim3(256), 0, stream, hist, n_buckets, sums);
-    hipLaunchKernelGGL(hrr::scan_sums_kernel, dim3(1), dim3(256), 0, stream, sums, n_chunks);
-    hipLaunchKernelGGL(hrr::scan_apply_kernel, dim3(n_chunks), dim3(256), 0, stream, hist, n_buckets, sums);
+    if ((e = hrr::scan::exclusive_sum(hist, hist, n_buckets, hist + n_buckets, stream)) != hipSuccess) return e;
     hipLaunchKernelGGL(hrr::order_scatter_kernel, dim3(blocks), dim3(256), 0, stream, keys, vbegin, total, key_bits,
                        hist, order);
     return hipGetLastError();
