@@ -138,7 +138,7 @@ hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint32_t* b,
 typedef struct hrr_hierarchy_info {
     uint32_t n_lights;
     uint32_t leaf_size;
-    uint32_t n_nodes;       /* internal nodes */
+    uint32_t n_nodes;       /* node records (sibling pairs, see hrr_hierarchy_records) */
     uint32_t depth;         /* deepest internal node (root = 0) */
     uint64_t device_bytes;  /* nodes + sorted lights + permutation */
     float box[6];           /* root bounding box lo xyz, hi xyz */
@@ -170,7 +170,7 @@ hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz,
  * caches that already live in device memory): lights_xyz_dev is device
  * memory, 3*n_lights fp32; box and leaf_size (with its split flag) as above.  The result is the
  * one hrr_build_hierarchy returns for the same lights, record for record
- * (same order, splits, exact boxes and preorder numbering): Morton codes,
+ * (same order, splits, exact boxes and record numbering): Morton codes,
  * a stable radix sort, one launch per tree level for the splits, then a
  * bottom-up refit.  Work is ordered on `stream`; the call returns when the
  * hierarchy is complete.  Non-finite coordinates return HRR_E_INVALID. */
@@ -178,12 +178,15 @@ hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* lights_xyz_dev,
                                       uint32_t n_lights, uint32_t leaf_size,
                                       const float* box, void* stream, hrr_hierarchy** out);
 hrr_status hrr_hierarchy_get_info(const hrr_hierarchy* h, hrr_hierarchy_info* out);
-/* nodes_out (host, 64 bytes per internal node): the node records in preorder.
- * Each holds the left child's box (lo xyz, then its first index a), the right
- * child's box (hi xyz of the left box, then the split c; lo xyz of the right
- * box, then the end b; hi xyz of the right box, then the right child's record
- * number or 0xFFFFFFFF for a leaf).  The left child, when internal, is the
- * next record. */
+/* nodes_out (host, 64 bytes per record, n_nodes records).  A record is one
+ * internal node [a, b) split at c: lo xyz of the left child's box, a; hi xyz
+ * of the left box, c; lo xyz of the right child's box, b; hi xyz of the right
+ * box, first.  Records sit in 128-byte sibling pairs: the root is record 0
+ * (record 1 is unused), and a node with an internal child owns records first
+ * (its left child, when internal) and first + 1 (its right child, when
+ * internal); pairs follow the depth-first preorder of their owners.  first is
+ * 0xFFFFFFFF when both children are leaves (at most leaf_size lights); an
+ * unused record is all zero. */
 hrr_status hrr_hierarchy_records(const hrr_hierarchy* h, void* nodes_out);
 /* perm_out (host u32[n_lights]): perm_out[i] = original index of the light
  * with sequence index i. */

@@ -189,7 +189,7 @@ def u32_tensor(a, device):
 
 
 NODE_DTYPE = np.dtype([("lo_l", "<f4", 3), ("a", "<u4"), ("hi_l", "<f4", 3), ("c", "<u4"),
-                       ("lo_r", "<f4", 3), ("b", "<u4"), ("hi_r", "<f4", 3), ("right", "<u4")])
+                       ("lo_r", "<f4", 3), ("b", "<u4"), ("hi_r", "<f4", 3), ("first", "<u4")])
 
 
 class Hierarchy:
@@ -221,7 +221,7 @@ class Hierarchy:
         return out
 
     def records(self) -> np.ndarray:
-        """Node records in preorder as a structured array (see include/hrr.h)."""
+        """Node records (sibling pairs, see include/hrr.h) as a structured array."""
         out = np.zeros(self.n_nodes, NODE_DTYPE)
         _check(_lib.hrr_hierarchy_records(self.handle, out.ctypes.data_as(_P)), "hierarchy records")
         return out

@@ -102,16 +102,20 @@ struct Builder {
         return hi;
     }
 
-    // Builds [a,b); returns its box.  Internal nodes get preorder numbers.
-    Box build(uint32_t a, uint32_t b, uint32_t depth) {
-        if (b - a <= leaf) return box_of(xyz, a, b);
+    // Builds the internal node [a,b) into record `me`; returns its box.  A
+    // node with an internal child takes the next sibling pair of records
+    // when it is built (pairs in preorder of their owners).
+    Box build(uint32_t a, uint32_t b, uint32_t depth, uint32_t me) {
         depth_max = std::max(depth_max, depth);
-        const uint32_t me = (uint32_t)nodes.size();
-        nodes.emplace_back();
         const uint32_t c = split(a, b);
-        const Box bl = build(a, c, depth + 1);
-        const uint32_t right = (uint32_t)nodes.size();
-        const Box br = build(c, b, depth + 1);
+        const bool in_l = c - a > leaf, in_r = b - c > leaf;
+        uint32_t first = 0xFFFFFFFFu;
+        if (in_l || in_r) {
+            first = (uint32_t)nodes.size();
+            nodes.resize(first + 2);
+        }
+        const Box bl = in_l ? build(a, c, depth + 1, first) : box_of(xyz, a, c);
+        const Box br = in_r ? build(c, b, depth + 1, first + 1) : box_of(xyz, c, b);
         Node& n = nodes[me];
         for (int k = 0; k < 3; ++k) {
             n.lo_l[k] = bl.lo[k];
@@ -122,7 +126,7 @@ struct Builder {
         n.a = a;
         n.c = c;
         n.b = b;
-        n.right = (b - c > leaf) ? right : 0xFFFFFFFFu;
+        n.first = first;
         return merge(bl, br);
     }
 };
@@ -166,9 +170,15 @@ bool build_hierarchy(const float* xyz, uint32_t n, uint32_t leaf, bool pow2, con
         for (int k = 0; k < 6; ++k) out.box[k] = 0.0f;
         return true;
     }
-    out.nodes.reserve(n > leaf ? (size_t)(2 * (n / leaf) + 2) : 1);
     Builder B{code, out.sorted_xyz, leaf, pow2, out.nodes};
-    const Box root = B.build(0, n, 0);
+    Box root;
+    if (n <= leaf) {
+        root = box_of(out.sorted_xyz, 0, n);
+    } else {
+        out.nodes.reserve(2 * (size_t)(n / leaf) + 2);
+        out.nodes.resize(2);   // the root, and the unused record 1
+        root = B.build(0, n, 0, 0);
+    }
     out.depth = B.depth_max;
     for (int k = 0; k < 3; ++k) {
         out.box[k] = root.lo[k];

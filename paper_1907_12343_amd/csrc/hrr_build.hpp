@@ -12,7 +12,7 @@ namespace hrr {
 struct HostHierarchy {
     uint32_t n_lights = 0, leaf_size = 1, depth = 0;
     bool pow2 = false;                // split rule: largest power of two below the length
-    std::vector<Node> nodes;          // internal nodes, preorder
+    std::vector<Node> nodes;          // node records in sibling pairs (hrr_types.hpp)
     std::vector<float> sorted_xyz;    // 3 per light, sequence order
     std::vector<uint32_t> perm;       // perm[i] = original index of sequence index i
     float box[6] = {0, 0, 0, 0, 0, 0};

@@ -2,7 +2,7 @@
 // record identical to the host builder (hrr_build.cpp): same Morton codes,
 // same (code, original index) order, same split rule (radix split with the
 // midpoint for equal codes, or the power-of-two split), same exact fp32 boxes
-// and the same depth-first preorder numbering.
+// and the same record numbering (sibling pairs in preorder of their owners).
 //
 // Section 1 of the paper only needs the lights sorted by a spatial hierarchy
 // with every node a contiguous index range; building it on the device lets a
@@ -17,10 +17,11 @@
 //                level (exclusive scan of the child counts)
 //   5. refit   : deepest level first, each node's children boxes (a leaf
 //                child from its <= leaf_size lights, an internal child as
-//                the union of its own children) and its internal-node count
-//   6. records : root level first, preorder numbers (left = self + 1,
-//                right = self + 1 + internal nodes of the left subtree) and
-//                the 64-byte records at those numbers
+//                the union of its own children) and the number of pair
+//                owners (nodes with an internal child) in its subtree
+//   6. records : root level first, record numbers (a node's children take
+//                the sibling pair 2 (1 + owners before it in preorder) and
+//                the next record) and the 64-byte records at those numbers
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -76,8 +77,9 @@ __global__ void gather_kernel(const float* __restrict__ xyz, const uint32_t* __r
 //
 // Internal nodes are numbered breadth-first (t); level l holds
 // [off[l], off[l+1]).  Bfs (hrr_devbuild.hpp) holds, per node, the range a,
-// split c, end b, children t (or -1 for a leaf child), subtree counts,
-// preorder numbers and the node's own box.
+// split c, end b, children t (or -1 for a leaf child), subtree counts of
+// pair owners, record numbers, owners before the node in preorder and the
+// node's own box.
 
 __device__ __forceinline__ uint32_t split_of(const uint64_t* __restrict__ code, uint32_t a, uint32_t b,
                                              uint32_t pow2) {
@@ -165,7 +167,7 @@ __device__ __forceinline__ void child_box(const Bfs& T, const float4* __restrict
     }
 }
 
-// Refit one level (deepest first): own box and internal-node count.
+// Refit one level (deepest first): own box and the pair owners in the subtree.
 __global__ void refit_kernel(Bfs T, const float4* __restrict__ lights, uint32_t t0, uint32_t t1) {
     const uint32_t t = t0 + blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= t1) return;
@@ -179,11 +181,11 @@ __global__ void refit_kernel(Bfs T, const float4* __restrict__ lights, uint32_t 
         bx[k] = min_first(llo[k], rlo[k]);
         bx[3 + k] = max_first(lhi[k], rhi[k]);
     }
-    T.cnt[t] = 1u + (l >= 0 ? T.cnt[l] : 0u) + (r >= 0 ? T.cnt[r] : 0u);
+    T.cnt[t] = (l >= 0 || r >= 0 ? 1u : 0u) + (l >= 0 ? T.cnt[l] : 0u) + (r >= 0 ? T.cnt[r] : 0u);
 }
 
-// Records of one level (root level first): children's preorder numbers and
-// the 64-byte record at this node's number.
+// Records of one level (root level first): the children's record numbers
+// and owner ranks, and the 64-byte record at this node's number.
 __global__ void record_kernel(Bfs T, const float4* __restrict__ lights, uint32_t t0, uint32_t t1,
                               Node* __restrict__ nodes) {
     const uint32_t t = t0 + blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,11 +193,18 @@ __global__ void record_kernel(Bfs T, const float4* __restrict__ lights, uint32_t
     const uint32_t me = T.pre[t];
     const uint32_t a = T.a[t], c = T.c[t], b = T.b[t];
     const int32_t l = T.l[t], r = T.r[t];
-    uint32_t right = 0xFFFFFFFFu;
-    if (l >= 0) T.pre[l] = me + 1u;
-    if (r >= 0) {
-        right = me + 1u + (l >= 0 ? T.cnt[l] : 0u);
-        T.pre[r] = right;
+    uint32_t first = 0xFFFFFFFFu;
+    if (l >= 0 || r >= 0) {
+        const uint32_t rank = T.own[t];   // owners before this node in preorder
+        first = 2u * (1u + rank);
+        if (l >= 0) {
+            T.pre[l] = first;
+            T.own[l] = rank + 1u;
+        }
+        if (r >= 0) {
+            T.pre[r] = first + 1u;
+            T.own[r] = rank + 1u + (l >= 0 ? T.cnt[l] : 0u);
+        }
     }
     float llo[3], lhi[3], rlo[3], rhi[3];
     child_box(T, lights, l, a, c, llo, lhi);
@@ -210,7 +219,7 @@ __global__ void record_kernel(Bfs T, const float4* __restrict__ lights, uint32_t
     nd.a = a;
     nd.c = c;
     nd.b = b;
-    nd.right = right;
+    nd.first = first;
     nodes[me] = nd;
 }
 
@@ -223,6 +232,7 @@ __global__ void init_root_kernel(Bfs T, uint32_t n) {
         T.a[0] = 0u;
         T.b[0] = n;
         T.pre[0] = 0u;
+        T.own[0] = 0u;
     }
 }
 

@@ -89,11 +89,12 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
         hrr_free_hierarchy(ctx, h);
         return st;
     };
-    if ((e = hipMalloc((void**)&h->d_nodes, std::max<size_t>(max_internal, 1) * sizeof(Node))) != hipSuccess ||
+    // node records: allocated once their number is known (after the refit)
+    if ((max_internal == 0 && (e = hipMalloc((void**)&h->d_nodes, sizeof(Node))) != hipSuccess) ||
         (e = hipMalloc((void**)&h->d_lights, std::max<size_t>(n, 1) * 4 * sizeof(float))) != hipSuccess ||
         (e = hipMalloc((void**)&h->d_perm, std::max<size_t>(n, 1) * sizeof(uint32_t))) != hipSuccess)
         return fail_free(hip_fail(e, "hierarchy allocation"));
-    h->device_bytes = std::max<size_t>(max_internal, 1) * sizeof(Node) + std::max<size_t>(n, 1) * 20;
+    h->device_bytes = (max_internal == 0 ? sizeof(Node) : 0) + std::max<size_t>(n, 1) * 20;
 
     Temps tmp;
     uint64_t *code_in = nullptr, *code = nullptr;
@@ -108,7 +109,7 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
         ((e = tmp.get(&T.a, max_internal)) != hipSuccess || (e = tmp.get(&T.c, max_internal)) != hipSuccess ||
          (e = tmp.get(&T.b, max_internal)) != hipSuccess || (e = tmp.get(&T.l, max_internal)) != hipSuccess ||
          (e = tmp.get(&T.r, max_internal)) != hipSuccess || (e = tmp.get(&T.cnt, max_internal)) != hipSuccess ||
-         (e = tmp.get(&T.pre, max_internal)) != hipSuccess || (e = tmp.get(&T.box, 6 * (size_t)max_internal)) != hipSuccess ||
+         (e = tmp.get(&T.pre, max_internal)) != hipSuccess || (e = tmp.get(&T.own, max_internal)) != hipSuccess || (e = tmp.get(&T.box, 6 * (size_t)max_internal)) != hipSuccess ||
          (e = tmp.get(&kids, max_internal)) != hipSuccess || (e = tmp.get(&prefix, max_internal)) != hipSuccess))
         return fail_free(hip_fail(e, "build scratch"));
     if ((e = hipHostMalloc((void**)&pin, 16 * sizeof(uint32_t), hipHostMallocDefault)) != hipSuccess)
@@ -169,13 +170,24 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
             if ((e = hrr_dev_refit(T, reinterpret_cast<const float4*>(h->d_lights), off[L], off[L + 1], stream)) !=
                 hipSuccess)
                 return fail_free(hip_fail(e, "refit"));
+        // records: the root, the unused record 1, then one sibling pair per
+        // node with an internal child (the root's subtree count)
+        if ((e = hipMemcpyAsync(pin + 3, T.cnt, sizeof(uint32_t), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess)
+            return fail_free(hip_fail(e, "record count"));
+        if (pin[3] > max_internal) return fail_free(fail(HRR_E_DEVICE, "device build: record count overflow"));
+        const uint32_t n_records = 2u * (1u + pin[3]);
+        if ((e = hipMalloc((void**)&h->d_nodes, (size_t)n_records * sizeof(Node))) != hipSuccess ||
+            (e = hipMemsetAsync(h->d_nodes, 0, (size_t)n_records * sizeof(Node), stream)) != hipSuccess)
+            return fail_free(hip_fail(e, "node records"));
+        h->device_bytes += (size_t)n_records * sizeof(Node);
         for (size_t L = 0; L < levels; ++L)
             if ((e = hrr_dev_records(T, reinterpret_cast<const float4*>(h->d_lights), off[L], off[L + 1], h->d_nodes,
                                      stream)) != hipSuccess)
                 return fail_free(hip_fail(e, "records"));
         if ((e = hipMemcpyAsync(d_box, T.box, 6 * sizeof(float), hipMemcpyDeviceToDevice, stream)) != hipSuccess)
             return fail_free(hip_fail(e, "root box"));
-        h->n_nodes = t1;
+        h->n_nodes = n_records;
         h->depth = (uint32_t)(levels - 1);
     } else if (n) {
         if ((e = hrr_dev_root_leaf_box(reinterpret_cast<const float4*>(h->d_lights), n, d_box, stream)) != hipSuccess)

@@ -14,8 +14,9 @@ struct Bfs {
     uint32_t* b;
     int32_t* l;      // breadth-first number of the internal left child, or -1
     int32_t* r;      // same for the right child
-    uint32_t* cnt;   // internal nodes in the subtree
-    uint32_t* pre;   // depth-first preorder number (the record index)
+    uint32_t* cnt;   // pair owners (nodes with an internal child) in the subtree
+    uint32_t* pre;   // record number
+    uint32_t* own;   // pair owners before the node in depth-first preorder
     float* box;      // 6 floats per node: lo xyz, hi xyz of its own box
 };
 

@@ -571,15 +571,15 @@ __device__ __forceinline__ void leaf_lights(OutState& O, const ItemDesc& D, cons
     }
 }
 
-// The walk is bound by instruction issue and the vector-memory pipeline, so
-// resident waves matter more than a few spilled registers: ask for 8 waves
-// per SIMD (at most 64 VGPRs) for the one-eye-per-wave form (frame: 145 ms
-// against 147 ms with 7 waves and 157 ms with 5).  The form that also writes
-// 1/p weights would spill inside the loop at 64 VGPRs: it asks for 7
-// (frame with weights 164.7 -> 145.4 ms; 148 ms with 6).
+// Occupancy.  With one eye per wave the LDS holds 7 waves per SIMD (a wave
+// takes its stack ring and the 4160-byte record area, 5696 bytes at the
+// default 192 entries; 28 waves fill 160 KB), so the register budget is the
+// one of 7 waves (72 VGPRs): asking for 8 only forced spills (frame
+// 108.6 -> 108.3 ms with 7).  Several eyes per wave use little LDS and run
+// at whatever occupancy their registers allow.
 template <int EPW, int METHOD, bool STATS, bool W>
 __global__ __launch_bounds__(kWave * kWavesPerBlock)
-__attribute__((amdgpu_waves_per_eu(EPW == 1 ? (W ? 7 : 8) : 1, 8)))
+__attribute__((amdgpu_waves_per_eu(EPW == 1 ? 7 : 1, 8)))
 void traverse_kernel(TravArgs A) {
     extern __shared__ __align__(16) unsigned char smem[];
     // dynamic LDS: task table (n_items + 1 entries, padded to 16 bytes), then one area per wave
@@ -756,7 +756,7 @@ void traverse_kernel(TravArgs A) {
             uint32_t kL = __builtin_nondeterministic_value(kL), kR = __builtin_nondeterministic_value(kR);
             uint32_t a = __builtin_nondeterministic_value(a), c = __builtin_nondeterministic_value(c);
             uint32_t b = __builtin_nondeterministic_value(b);
-            uint32_t rightIdx = __builtin_nondeterministic_value(rightIdx);
+            uint32_t first = __builtin_nondeterministic_value(first);
             float wL = __builtin_nondeterministic_value(wL), wR = __builtin_nondeterministic_value(wR);
             uint32_t mlN = 0, mrN = 0;   // lights of the multi-light leaves to test (0: none)
             // Node records.  A load costs about one cycle of the vector-memory
@@ -768,7 +768,7 @@ void traverse_kernel(TravArgs A) {
                 // lane 4g + j fetches quarter j of the records of lanes 4g + t;
                 // quarter j of record t lands at t * kSlab + 64 g + 16 j.
                 // Inactive lanes fetch record 0, so no load needs a lane mask;
-                // byte offsets are 32-bit (records of at most 2^26 nodes), the
+                // byte offsets are 32-bit (at most 2^26 records), the
                 // base and the LDS destinations are wave-uniform.
                 const uint32_t j = lane & 3u, g4 = lane & ~3u;
                 const uint32_t nd = act ? node : 0u;
@@ -820,7 +820,7 @@ void traverse_kernel(TravArgs A) {
                 a = __float_as_uint(q0.w);
                 c = __float_as_uint(q1.w);
                 b = __float_as_uint(q2.w);
-                rightIdx = __float_as_uint(q3.w);
+                first = __float_as_uint(q3.w);
                 const uint32_t k = e.y;
                 // the child holding k inherits the minimum; the other one needs a query
                 const bool kLeft = k < c;
@@ -880,8 +880,8 @@ void traverse_kernel(TravArgs A) {
                 // S.n + npush <= cap here, so S.base + at < 2 cap
                 const uint32_t at = S.n + count_below(bl) + count_below(br);
                 const uint32_t tag = (EPW > 1 ? slot : 0u) << kSlotShift;
-                if (pushL) L.stack[ring(S.base + at, cap)] = make_uint2((node + 1u) | tag, kL);
-                if (pushR) L.stack[ring(S.base + at + (pushL ? 1u : 0u), cap)] = make_uint2(rightIdx | tag, kR);
+                if (pushL) L.stack[ring(S.base + at, cap)] = make_uint2(first | tag, kL);
+                if (pushR) L.stack[ring(S.base + at + (pushL ? 1u : 0u), cap)] = make_uint2((first + 1u) | tag, kR);
                 S.n += npush;
                 wave_sync();
                 const uint32_t tot = S.g + S.n;

@@ -10,10 +10,18 @@ namespace hrr {
 // line).  The node covers sequence indices [a, b) (Section 1: a node is a
 // contiguous sub-range of the sorted lights) and is split at c into
 // [a, c) and [c, b).  It stores the fp32 bounding boxes of BOTH children, so
-// one 64-byte fetch lets a lane bound and cull two subtrees.  Internal nodes
-// are numbered in depth-first preorder: the left child, when internal, is
-// this node + 1; `right` is the right child's number when internal.  A child
-// whose range has at most leaf_size lights is a leaf and has no record.
+// one 64-byte fetch lets a lane bound and cull two subtrees.  A child whose
+// range has at most leaf_size lights is a leaf and has no record.
+//
+// Records sit in sibling pairs: the root is record 0 (record 1 is unused),
+// and a node with at least one internal child owns the pair of records
+// `first` (its left child, when internal) and `first` + 1 (its right child,
+// when internal), 128-byte aligned, so both children's records share one
+// cache line: when a walk descends into both children, as it does for about
+// two of every five records it reads, one line serves both.  Pairs are
+// numbered in depth-first preorder of their owners (subtrees stay contiguous
+// in memory).  A record slot whose child is a leaf is all zero, as is record
+// 1; `first` is 0xFFFFFFFF when both children are leaves.
 struct alignas(64) Node {
     float lo_l[3];
     uint32_t a;
@@ -22,7 +30,7 @@ struct alignas(64) Node {
     float lo_r[3];
     uint32_t b;
     float hi_r[3];
-    uint32_t right;
+    uint32_t first;
 };
 static_assert(sizeof(Node) == 64, "node record must be 64 bytes");
 
@@ -107,9 +115,10 @@ constexpr uint32_t kMinChunkShift = 7;  // a chunk holds >= 128 pairs (one emiss
 constexpr uint32_t kMaxChunkShift = 13;
 constexpr uint32_t kSlotShift = 28;     // stack entry: node | slot << 28
 constexpr uint32_t kMaxNodes = 1u << kSlotShift;
-// Lights per hierarchy: at most 2^26 - 1, so that the node records (64 bytes
-// each) span at most 4 GiB and the walk addresses them with 32-bit offsets.
-constexpr uint32_t kMaxLights = 1u << 26;
+// Lights per hierarchy: at most 2^25 - 1, so that the node records (64 bytes
+// each, at most 2 n_lights of them with the unused pair slots) span less than
+// 4 GiB and the walk addresses them with 32-bit offsets.
+constexpr uint32_t kMaxLights = 1u << 25;
 
 // Scratch of the allocation-free traversal (hrr_traverse_noalloc): one
 // device array per GPU, 128 MiB, laid out as a header (queue heads, counters,

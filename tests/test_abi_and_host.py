@@ -5,7 +5,7 @@
 * The host hierarchy builder (compiled here for the CPU, with no HIP) orders
   lights exactly like the oracle's own Morton sort and produces a valid
   hierarchy: children partition their parent's range at the radix split, the
-  boxes are the exact bounds of their lights, internal nodes are in preorder.
+  boxes are the exact bounds of their lights, records sit in sibling pairs.
 """
 import ctypes
 import os
@@ -94,7 +94,7 @@ int main() {
     printf("%zu %u\n", H.nodes.size(), H.depth);
     for (unsigned i = 0; i < n; ++i) printf("%u\n", H.perm[i]);
     for (auto& d : H.nodes) {
-        printf("%u %u %u %u", d.a, d.c, d.b, d.right);
+        printf("%u %u %u %u", d.a, d.c, d.b, d.first);
         for (int k = 0; k < 3; ++k) printf(" %a %a %a %a", d.lo_l[k], d.hi_l[k], d.lo_r[k], d.hi_r[k]);
         printf("\n");
     }
@@ -126,10 +126,10 @@ def _run_builder(exe, lights, leaf, pow2=False):
     nodes = []
     for ln in lines[1 + n:1 + n + n_nodes]:
         f = ln.split()
-        a, c, b, right = (int(x) for x in f[:4])
+        a, c, b, first = (int(x) for x in f[:4])
         vals = [float.fromhex(x) for x in f[4:]]
         lo_l = vals[0::4]; hi_l = vals[1::4]; lo_r = vals[2::4]; hi_r = vals[3::4]
-        nodes.append((a, c, b, right, lo_l, hi_l, lo_r, hi_r))
+        nodes.append((a, c, b, first, lo_l, hi_l, lo_r, hi_r))
     return perm, nodes, depth
 
 
@@ -140,7 +140,9 @@ def test_host_builder_matches_oracle_order_and_is_valid(orc, build_harness, n, l
     """Order = the oracle's Morton order; every split follows its rule (radix:
     the highest differing code bit, midpoint for equal codes; power of two:
     the left child holds the largest power of two below the length); exact
-    child boxes; preorder numbering; the recorded depth."""
+    child boxes; sibling-pair records (a node with an internal child owns
+    the aligned pair first, first + 1, pairs in preorder of their owners,
+    unused slots all zero); the recorded depth."""
     if seed == 6:   # many coincident lights: equal codes split at the midpoint
         lights = np.repeat(synth.uniform_points(8, seed), 8, axis=0)
     else:
@@ -152,13 +154,15 @@ def test_host_builder_matches_oracle_order_and_is_valid(orc, build_harness, n, l
     if n <= leaf:
         assert nodes == []
         return
-    # preorder numbering: left internal child is next; right as recorded
+    # sibling pairs: the root is record 0, record 1 unused; an owner's pair
+    # is the next one in preorder of the owners
     seen = set()
+    owners = []
 
     def walk(idx, a, b, d):
         assert idx not in seen
         seen.add(idx)
-        na, c, nb, right, lo_l, hi_l, lo_r, hi_r = nodes[idx]
+        na, c, nb, first, lo_l, hi_l, lo_r, hi_r = nodes[idx]
         assert (na, nb) == (a, b) and a < c < b
         if pow2:
             k = 1 << ((b - a - 1).bit_length() - 1)   # largest power of two below b - a
@@ -174,14 +178,23 @@ def test_host_builder_matches_oracle_order_and_is_valid(orc, build_harness, n, l
             assert np.array_equal(np.array(lo, np.float32), ls[s:e].min(axis=0))
             assert np.array_equal(np.array(hi, np.float32), ls[s:e].max(axis=0))
         dd = d
-        if c - a > leaf:
-            dd = max(dd, walk(idx + 1, a, c, d + 1))
-        if b - c > leaf:
-            dd = max(dd, walk(right, c, b, d + 1))
+        if c - a > leaf or b - c > leaf:
+            owners.append(idx)
+            assert first == 2 * len(owners)
+        else:
+            assert first == 0xFFFFFFFF
+        for (child, s, e) in ((first, a, c), (first + 1, c, b)):
+            if e - s > leaf:
+                dd = max(dd, walk(child, s, e, d + 1))
+            elif first != 0xFFFFFFFF:
+                assert nodes[child][:4] == (0, 0, 0, 0) and not any(any(v) for v in nodes[child][4:])
+                seen.add(child)
         return dd
 
     assert walk(0, 0, n, 0) == depth
-    assert len(seen) == len(nodes)
+    assert nodes[1][:4] == (0, 0, 0, 0) and not any(any(v) for v in nodes[1][4:])
+    seen.add(1)
+    assert len(seen) == len(nodes) == 2 * (1 + len(owners))
 
 
 ARENA_HARNESS = r"""

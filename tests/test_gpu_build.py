@@ -1,5 +1,5 @@
 """GPU hierarchy build: the same hierarchy as the host builder, record for
-record (order, splits, exact fp32 boxes, preorder numbering), and traversals
+record (order, splits, exact fp32 boxes, record numbering), and traversals
 on it equal the all-pairs oracle."""
 import numpy as np
 import pytest
