@@ -370,9 +370,12 @@ def batched_workload(args, steps=None, warmup=None):
     """256 independent caches (own mixture, 2^U[10,20] lights, 2^U[10,16]
     eyes, s = 1e-4) in ONE call -- one persistent launch per eyes-per-wave
     group of the items -- against 256 plain launches of the same items on the
-    same GPU.  The leaf size comes from the autotuner, run once before timing
-    on the cache with the most estimated work (eyes x lights^0.6); every
-    group's own ALU fraction is measured with a call of that group alone."""
+    same GPU.  Before timing, the batched autotuner runs once per light
+    class (log2 of the light count) on all caches of the class together, over
+    leaf sizes 1, 2, 4, 8 and the launch shapes; every cache is built with
+    its class's leaf size, and the call groups the items by their classes'
+    eyes per wave.  Every group's own ALU fraction is measured with a call of
+    that group alone."""
     import numpy as np
     import torch
     import paper_1907_12343_amd as hrr
@@ -383,18 +386,23 @@ def batched_workload(args, steps=None, warmup=None):
     ctx = hrr.Context(synth.dither_tile(100), device=0)
     caches = [synth.batched_cache(c) for c in range(256)]
     sizes = np.array([d["lights"].shape[0] for d in caches])
-    work = np.array([d["eyes"].shape[0] * d["lights"].shape[0] ** 0.6 for d in caches])
-    probe = caches[int(np.argmax(work))]   # tune on the cache that dominates the launch
+    lclass = np.array([int(n).bit_length() - 1 for n in sizes])
     t0 = time.time()
-    cand = [ctx.build_hierarchy(probe["lights"], leaf_size=L, split=args.split) for L in (1, 2, 4, 8)]
-    pe = torch.from_numpy(probe["eyes"]).to("cuda:0")
-    tuned = ctx.autotune(cand, pe, probe["s"], probe["width"], max_probe_eyes=32768)
-    for h in cand:
-        h.free()
-    leaf = tuned["leaf_size"]
-    hs = [ctx.build_hierarchy(d["lights"], leaf_size=leaf, split=args.split) for d in caches]
-    setup_s = time.time() - t0
     eyes = [torch.from_numpy(d["eyes"]).to("cuda:0") for d in caches]
+    tuned = {}
+    for c in sorted(set(lclass.tolist())):
+        ks = np.flatnonzero(lclass == c)
+        sets = []
+        for L in (1, 2, 4, 8):
+            sets.append([dict(h=ctx.build_hierarchy(caches[k]["lights"], leaf_size=L, split=args.split),
+                              eyes=eyes[k], s=caches[k]["s"], width=caches[k]["width"]) for k in ks])
+        tuned[c] = ctx.autotune_batched(sets)
+        for st_ in sets:
+            for it in st_:
+                it["h"].free()
+    leaves = [tuned[int(c)]["leaf_size"] for c in lclass]
+    hs = [ctx.build_hierarchy(d["lights"], leaf_size=L, split=args.split) for d, L in zip(caches, leaves)]
+    setup_s = time.time() - t0
     counts = [ctx.count(h, e, d["s"], d["width"]) for h, e, d in zip(hs, eyes, caches)]
     offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
     total = int(offs[-1])
@@ -423,13 +431,11 @@ def batched_workload(args, steps=None, warmup=None):
     ms_plain, _ = timed_launches(plain, max(1, steps // 4), 1)
     ops = lane_ops(st, total)
 
-    # the groups alone (same grouping rule as the call: eyes per wave by light class)
+    # the groups alone (the call's grouping: the eyes per wave tuned for the class)
     groups = {}
-    for k, d in enumerate(caches):
-        nl = d["lights"].shape[0]
-        g = "1 eye/wave (>= 2^17 lights)" if nl >= 1 << 17 else (
-            "4 eyes/wave (2^16..2^17 lights)" if nl >= 1 << 16 else "8 eyes/wave (< 2^16 lights)")
-        groups.setdefault(g, []).append(k)
+    for k in range(len(caches)):
+        e = tuned[int(lclass[k])]["eyes_per_wave"]
+        groups.setdefault("%d eye%s/wave" % (e, "" if e == 1 else "s"), []).append(k)
     per_group = {}
     for g, ks in groups.items():
         sub = [items[k] for k in ks]
@@ -444,6 +450,7 @@ def batched_workload(args, steps=None, warmup=None):
         g_ms = sum(gk[warmup:]) / max(len(gk) - warmup, 1)
         g_pairs = int(sum(counts[k] for k in ks))
         per_group[g] = {"items": len(ks), "eyes": int(sum(caches[k]["eyes"].shape[0] for k in ks)),
+                        "light_classes": sorted({int(lclass[k]) for k in ks}),
                         "pairs": g_pairs, "kernel_ms": g_ms,
                         "alu_frac": alu_roofline(lane_ops(sst, g_pairs), g_ms)["frac"]}
     line = {
@@ -454,8 +461,9 @@ def batched_workload(args, steps=None, warmup=None):
         "config": {"workload": "batched: 256 caches, own 64-Gaussian mixture each, 2^U[10,20] "
                                "lights, 2^U[10,16] eyes, s=1e-4, one call (a launch per "
                                "eyes-per-wave group)",
-                   "n_eyes": n_eyes, "n_lights": int(sizes.sum()), "leaf": leaf, "split": args.split,
-                   "tuned": tuned, "parallelism": "1 GPU"},
+                   "n_eyes": n_eyes, "n_lights": int(sizes.sum()), "split": args.split,
+                   "tuned_per_light_class": {"2^%d" % c: v for c, v in sorted(tuned.items())},
+                   "parallelism": "1 GPU"},
         "pairs_per_s": total / (ms * 1e-3), "accepted_pairs": total, "kernel_ms": gpu_ms,
         "step_gpu_ms": step_gpu_ms, "setup_s": setup_s,
         "plain_launches": {"ms_per_step": ms_plain, "eyes_per_s": n_eyes / (ms_plain * 1e-3),
@@ -466,7 +474,7 @@ def batched_workload(args, steps=None, warmup=None):
         "roofline": alu_roofline(ops, gpu_ms),
         "groups": per_group,
     }
-    del pairs, eyes, pe
+    del pairs, eyes
     for h in hs:
         h.free()
     ctx.close()
@@ -644,7 +652,8 @@ def all_workloads(args):
     head["batched"] = dict(_brief(bt, ("value", "unit", "ms_per_step", "kernel_ms", "pairs_per_s",
                                        "plain_launches", "units", "algorithmic_lane_ops",
                                        "roofline", "groups")),
-                           workload=bt["config"]["workload"], leaf=bt["config"]["leaf"])
+                           workload=bt["config"]["workload"],
+                           tuned_per_light_class=bt["config"]["tuned_per_light_class"])
     sv = served_workload(args)
     head["served"] = dict(_brief(sv, ("value", "unit", "saturation", "loads",
                                       "strict_fifo_admission_0.9", "plain_single_launches")),

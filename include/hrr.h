@@ -343,6 +343,21 @@ typedef struct hrr_tune_result {
 hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs, uint32_t n_h,
                         const hrr_eyes* eyes, float s, uint32_t max_probe_eyes,
                         hrr_tune_result* best, void* stream);
+/* Batched autotuner.  sets holds n_sets x n_items work items (host array,
+ * set-major): the same eye sets against the same lights in every set, set q
+ * built with its own leaf size (normally 1, 2, 4, 8).  For every set the
+ * call times ONE launch of all its items (their own eyes, a scratch output
+ * the library allocates; out_offset and out_capacity are ignored) for every
+ * eyes per wave and stack candidate, in the order and with the 2 % rule of
+ * hrr_autotune, and remembers the fastest (leaf size, eyes per wave, stack)
+ * for the light class and eye class of every item.  Meant for the items of
+ * one light class of a batch: a launch of all of them fills the GPU as the
+ * batched call will, which a probe launch of a single small cache does not.
+ * Later calls with eyes_per_wave = 0 or stack_entries = 0 use the remembered
+ * shape as above.  best (host, optional) receives the winner.  Synchronous;
+ * HRR_E_INVALID when a set's items differ from set 0 in lights or eyes. */
+hrr_status hrr_autotune_batched(hrr_ctx* ctx, const hrr_work_item* sets, uint32_t n_sets,
+                                uint32_t n_items, hrr_tune_result* best, void* stream);
 /* The leaf size the tuner prefers for hierarchies of n_lights lights (0 if none tuned). */
 uint32_t hrr_tuned_leaf_size(const hrr_ctx* ctx, uint32_t n_lights);
 

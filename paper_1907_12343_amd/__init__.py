@@ -110,6 +110,7 @@ SIGNATURES = {
     "hrr_traverse_batched": (_i32, [_P, _P, _u32, _P, _P, _P, _P, _P, _P]),
     "hrr_traverse_noalloc": (_i32, [_P, _P, _P, _f32, _P, _P, _P, _u64, _P, _P]),
     "hrr_autotune": (_i32, [_P, _P, _u32, _P, _f32, _u32, _P, _P]),
+    "hrr_autotune_batched": (_i32, [_P, _P, _u32, _u32, _P, _P]),
     "hrr_tuned_leaf_size": (_u32, [_P, _u32]),
     "hrr_server_start": (_i32, [_P, _P]),
     "hrr_server_stop": (_i32, [_P]),
@@ -433,6 +434,25 @@ class Context:
         _check(_lib.hrr_autotune(self.handle, arr, len(hs), ctypes.byref(E), float(s),
                                  max_probe_eyes, ctypes.byref(res), _stream_handle(stream)),
                "hrr_autotune")
+        return dict(eyes_per_wave=res.eyes_per_wave, stack_entries=res.stack_entries,
+                    leaf_size=res.leaf_size, ms=res.ms)
+
+    def autotune_batched(self, sets: Sequence[Sequence[dict]], stream=None):
+        """sets: equally long lists of dicts (h, eyes, s, width, [shift_offset,
+        pixel_base]), set q built with its own leaf size; see hrr_autotune_batched."""
+        n_items = len(sets[0])
+        if any(len(x) != n_items for x in sets):
+            raise ValueError("every set needs the same items")
+        arr = (HrrWorkItem * (len(sets) * n_items))()
+        keep = []
+        for q, items in enumerate(sets):
+            for k, it in enumerate(items):
+                E = self._eyes(it["eyes"], it["width"], it.get("shift_offset", 0), it.get("pixel_base", 0))
+                keep.append(it["eyes"])
+                arr[q * n_items + k] = HrrWorkItem(it["h"].handle, E, float(it["s"]), 0, 0, 0)
+        res = HrrTuneResult()
+        _check(_lib.hrr_autotune_batched(self.handle, arr, len(sets), n_items, ctypes.byref(res),
+                                         _stream_handle(stream)), "hrr_autotune_batched")
         return dict(eyes_per_wave=res.eyes_per_wave, stack_entries=res.stack_entries,
                     leaf_size=res.leaf_size, ms=res.ms)
 

@@ -607,6 +607,99 @@ HRR_EXPORT hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs,
     return HRR_OK;
 }
 
+HRR_EXPORT hrr_status hrr_autotune_batched(hrr_ctx* ctx, const hrr_work_item* sets, uint32_t n_sets, uint32_t n_items,
+                                           hrr_tune_result* best, void* stream) {
+    if (!ctx || !sets || n_sets == 0 || n_items == 0) return fail(HRR_E_INVALID, "hrr_autotune_batched: null argument");
+    for (uint32_t q = 0; q < n_sets; ++q)
+        for (uint32_t k = 0; k < n_items; ++k) {
+            const hrr_work_item& it = sets[(size_t)q * n_items + k];
+            if (!it.h || it.h->owner != ctx) return fail(HRR_E_INVALID, "hrr_autotune_batched: bad hierarchy %u/%u", q, k);
+            if (it.h->n_lights != sets[k].h->n_lights || it.eyes.n != sets[k].eyes.n)
+                return fail(HRR_E_INVALID, "hrr_autotune_batched: set %u item %u differs from set 0", q, k);
+        }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    static const uint32_t epws[] = {1, 2, 4, 8};
+    TuneVal bestv{0, 0, 0, 1e30f};
+    DevBuf out;
+    hipEvent_t e0, e1;
+    if ((e = hipEventCreate(&e0)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventCreate(&e1)) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(e, "event");
+    }
+    hrr_status result = HRR_OK;
+    std::vector<HostItem> items(n_items);
+    std::vector<uint64_t> cnt(n_items), c2(n_items);
+    for (uint32_t q = 0; q < n_sets && result == HRR_OK; ++q) {
+        for (uint32_t k = 0; k < n_items; ++k) {
+            const hrr_work_item& it = sets[(size_t)q * n_items + k];
+            items[k] = HostItem{it.h, it.eyes, it.s, 0, 0};
+        }
+        // count pass, then every item gets its slice of the scratch output
+        hrr_status r = run_sync(ctx, items, nullptr, nullptr, nullptr, cnt.data(), nullptr, st, 1,
+                                default_stack_entries(1));
+        if (r != HRR_OK && r != HRR_E_OVERFLOW) {
+            result = r;
+            break;
+        }
+        uint64_t total = 0;
+        for (uint32_t k = 0; k < n_items; ++k) {
+            items[k].out_offset = total;
+            items[k].out_capacity = cnt[k];
+            total += cnt[k];
+        }
+        if ((e = out.ensure(std::max<uint64_t>(total, 1) * 8)) != hipSuccess) {
+            result = hip_fail(e, "tuner output");
+            break;
+        }
+        for (uint32_t epw : epws) {
+            uint32_t caps[3];
+            tune_stack_candidates(epw, caps);
+            for (uint32_t cap : caps) {
+                float ms_best = 1e30f;
+                for (int rep = 0; rep < 2; ++rep) {
+                    (void)hipEventRecord(e0, st);
+                    r = run_sync(ctx, items, nullptr, static_cast<uint32_t*>(out.p), nullptr, c2.data(), nullptr, st,
+                                 epw, cap);
+                    (void)hipEventRecord(e1, st);
+                    (void)hipEventSynchronize(e1);
+                    if (r != HRR_OK) break;
+                    float ms = 0.f;
+                    (void)hipEventElapsedTime(&ms, e0, e1);
+                    ms_best = std::min(ms_best, ms);
+                }
+                if (r != HRR_OK) {
+                    result = r;
+                    break;
+                }
+                if (ms_best < bestv.ms * 0.98f) bestv = TuneVal{epw, cap, items[0].h->leaf_size, ms_best};
+            }
+            if (result != HRR_OK) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    out.release();
+    if (result != HRR_OK) return result;
+    {
+        std::lock_guard<std::mutex> g(ctx->tune_mu);
+        for (uint32_t k = 0; k < n_items; ++k) {
+            const int ll = ilog2_floor(sets[k].h->n_lights);
+            ctx->tune[TuneKey{ll, ilog2_floor(sets[k].eyes.n)}] = bestv;
+            ctx->tune_leaf[ll] = bestv.leaf_size;
+        }
+    }
+    if (best) {
+        best->eyes_per_wave = bestv.eyes_per_wave;
+        best->stack_entries = bestv.stack_entries;
+        best->leaf_size = bestv.leaf_size;
+        best->ms = bestv.ms;
+    }
+    return HRR_OK;
+}
+
 HRR_EXPORT uint32_t hrr_tuned_leaf_size(const hrr_ctx* ctx, uint32_t n_lights) {
     if (!ctx) return 0;
     hrr_ctx* c = const_cast<hrr_ctx*>(ctx);

@@ -331,6 +331,46 @@ def test_autotune_choice_is_valid_and_results_unchanged(hrr):
         ctx.close()
 
 
+def test_autotune_batched_choice_is_applied_and_results_unchanged(hrr):
+    """The batched tuner times one launch of all items per (leaf set, shape);
+    afterwards a batched call with eyes_per_wave = stack_entries = 0 runs
+    every item in the remembered shape, with the pairs of plain launches."""
+    ctx = hrr.Context(synth.dither_tile(TILE_SEED))
+    try:
+        import torch
+        ds = [_small_cache(c, 1 << 14, 1 << 11) for c in (7, 8, 9)]
+        es = [_dev(ctx, d["eyes"]) for d in ds]
+        sets = [[dict(h=ctx.build_hierarchy(d["lights"], leaf_size=L), eyes=e, s=d["s"],
+                      width=d["width"]) for d, e in zip(ds, es)] for L in (1, 2)]
+        best = ctx.autotune_batched(sets)
+        assert best["eyes_per_wave"] in (1, 2, 4, 8)
+        assert best["stack_entries"] in ((192, 256, 512) if best["eyes_per_wave"] == 1 else (256, 512, 1024))
+        assert best["leaf_size"] in (1, 2) and best["ms"] > 0
+        for d in ds:
+            assert ctx.tuned_leaf_size(d["lights"].shape[0]) == best["leaf_size"]
+        q = (1, 2).index(best["leaf_size"])
+        items = sets[q]
+        refs = [_plain_keys(ctx, it["h"], it["eyes"], it["s"], it["width"]) for it in items]
+        offs = np.concatenate([[0], np.cumsum([r.size for r in refs])]).astype(np.int64)
+        pairs = torch.empty((max(int(offs[-1]), 1), 2), dtype=torch.int32, device=ctx.torch_device)
+        bi = [dict(it, out_offset=int(offs[k]), out_capacity=int(refs[k].size)) for k, it in enumerate(items)]
+        counts, _ = ctx.traverse_batched(bi, pairs, eyes_per_wave=0, stack_entries=0)
+        for k in range(len(items)):
+            assert int(counts[k]) == refs[k].size
+            got = pair_keys_from_gpu(pairs[offs[k]:offs[k + 1]])
+            assert np.array_equal(got, refs[k]), k
+        # a set whose items differ from set 0 is refused
+        bad = [sets[0], [dict(sets[1][0], eyes=es[0][:100])] + sets[1][1:]]
+        with pytest.raises(hrr.HrrError):
+            ctx.autotune_batched(bad)
+        del pairs
+        for st in sets:
+            for it in st:
+                it["h"].free()
+    finally:
+        ctx.close()
+
+
 # ---------------------------------------------------------------------------
 # serving loop
 # ---------------------------------------------------------------------------
