@@ -306,7 +306,8 @@ typedef struct hrr_work_item {
  * resolved on its own (tuned entry of its light class or a neighbouring one,
  * else 8 eyes per wave below 2^16 lights, 4 below 2^17, then 1) and the call
  * enqueues one such launch per group of equal shape on `stream`, largest
- * hierarchies first.  items: host array.  counts_out (host u64[n_items])
+ * hierarchies first.  items: host array of at most 1024 items (HRR_E_INVALID
+ * beyond).  counts_out (host u64[n_items])
  * receives each item's true pair count; items whose count exceeds their
  * capacity store only the first out_capacity pairs and make the call return
  * HRR_E_OVERFLOW.  stats (optional) sums the work of all launches (max_stack:
@@ -355,7 +356,8 @@ hrr_status hrr_autotune(hrr_ctx* ctx, const hrr_hierarchy* const* hs, uint32_t n
  * batched call will, which a probe launch of a single small cache does not.
  * Later calls with eyes_per_wave = 0 or stack_entries = 0 use the remembered
  * shape as above.  best (host, optional) receives the winner.  Synchronous;
- * HRR_E_INVALID when a set's items differ from set 0 in lights or eyes. */
+ * HRR_E_INVALID when a set's items differ from set 0 in lights or eyes, or
+ * when n_items exceeds the 1024 items of one launch. */
 hrr_status hrr_autotune_batched(hrr_ctx* ctx, const hrr_work_item* sets, uint32_t n_sets,
                                 uint32_t n_items, hrr_tune_result* best, void* stream);
 /* The leaf size the tuner prefers for hierarchies of n_lights lights (0 if none tuned). */
