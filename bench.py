@@ -234,8 +234,11 @@ def frame_workload(args, split=None, cpu=True, steps=None, warmup=None):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traverse_frame_traffic.json")
 RMQ_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "range_min_traffic.json")
+# Everything that shapes the counted launches: the kernels and their headers,
+# the launch layout (eye order, queues) and the host build's record layout.
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1907_12343_amd", "csrc", f)
-                  for f in ("hrr_kernels.hip", "hrr_rmq.hpp", "hrr_types.hpp")]
+                  for f in ("hrr_kernels.hip", "hrr_rmq.hpp", "hrr_types.hpp", "hrr_compact.hpp",
+                            "hrr_scan.hpp", "hrr_layout.hpp", "hrr_launch.cpp", "hrr_build.cpp")]
 
 
 def kernel_source_digest():
