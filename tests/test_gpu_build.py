@@ -94,6 +94,22 @@ def test_device_build_frame_scale(ctx, split):
     hd.free()
 
 
+@pytest.mark.parametrize("split", ["radix", "pow2"])
+def test_device_build_largest_served_hierarchy(ctx, split):
+    """The served workload's largest hierarchy (2^22 lights of a Gaussian
+    mixture, radix depth about 40, many single-internal-child nodes): record
+    for record equal to the host build, holes of the sibling pairs included."""
+    sc = synth.served_hierarchy(15)
+    assert sc["lights"].shape[0] == 1 << 22
+    hh = ctx.build_hierarchy(sc["lights"], leaf_size=1, split=split)
+    hd = ctx.build_hierarchy_device(_dev(ctx, sc["lights"]), leaf_size=1, split=split)
+    _same(hh, hd)
+    if split == "pow2":
+        assert hh.n_nodes == 1 << 22   # a perfect tree fills every pair
+    hh.free()
+    hd.free()
+
+
 def test_device_build_rejects_bad_input(ctx, hrr):
     bad = np.random.default_rng(13).random((100, 3)).astype(np.float32)
     bad[57, 2] = np.inf
