@@ -517,8 +517,8 @@ def served_workload(args):
         return ctx.submit(hs[int(base["hier"][q])], req_eyes[q], 64, int(base["offset"][q]), s_val)
 
     def start(overtake_ms):
-        ctx.server_start(hbm_budget_bytes=int(args.budget_gib * (1 << 30)), max_inflight=2,
-                         max_batch_eyes=1 << 20, max_batch_items=64, pairs_per_eye_guess=2000.0,
+        ctx.server_start(hbm_budget_bytes=int(args.budget_gib * (1 << 30)), max_inflight=args.inflight,
+                         max_batch_eyes=args.batch_eyes, max_batch_items=64, pairs_per_eye_guess=2000.0,
                          overtake_ms=overtake_ms)
 
     def drain(tickets, out):
@@ -617,7 +617,8 @@ def served_workload(args):
         "config": {"workload": "served: 16 resident hierarchies 2^(16+6h/15) lights, Poisson "
                                "requests of 2^U[8,18] eyes, own shift offset, s=1e-4",
                    "requests": n_req, "budget_gib": args.budget_gib, "split": args.split,
-                   "overtake_ms": args.overtake_ms, "parallelism": "1 GPU"},
+                   "overtake_ms": args.overtake_ms, "workers": args.inflight,
+                   "max_batch_eyes": args.batch_eyes, "parallelism": "1 GPU"},
         "saturation": {"req_per_s": sat_rate, "eyes_per_s": sat_eyes, "pairs_per_s": sat_pairs},
         "loads": loads, "strict_fifo_admission_0.9": fifo_09, "plain_single_launches": plain,
         "server_stats": stats, "setup_s": setup_s, "roofline": None,
@@ -660,7 +661,8 @@ def all_workloads(args):
     sv = served_workload(args)
     head["served"] = dict(_brief(sv, ("value", "unit", "saturation", "loads",
                                       "strict_fifo_admission_0.9", "plain_single_launches")),
-                          workload=sv["config"]["workload"], overtake_ms=args.overtake_ms)
+                          workload=sv["config"]["workload"], overtake_ms=args.overtake_ms,
+                          workers=args.inflight, max_batch_eyes=args.batch_eyes)
     return head
 
 
@@ -675,6 +677,9 @@ def main():
     p.add_argument("--budget-gib", type=float, default=64.0, help="served: device arena")
     p.add_argument("--load-seconds", type=float, default=8.0,
                    help="served: seconds of arrivals per offered load")
+    p.add_argument("--inflight", type=int, default=2, help="served: worker threads (launches in flight)")
+    p.add_argument("--batch-eyes", type=int, default=1 << 16,
+                   help="served: eyes per batch at most (a larger request runs alone)")
     p.add_argument("--overtake-ms", type=float, default=100.0,
                    help="served: a queued request that does not fit is passed over by later "
                         "ones until it has waited this long (0 = strict FIFO admission)")
