@@ -397,7 +397,11 @@ uint32_t hrr_tuned_leaf_size(const hrr_ctx* ctx, uint32_t n_lights);
 typedef struct hrr_server_config {
     uint64_t hbm_budget_bytes;   /* device arena for request eyes + results (>= 1 MiB) */
     uint32_t max_inflight;       /* launches in flight at once (one worker + stream each), 1..8 */
-    uint32_t max_batch_eyes;     /* eyes per launch before a batch is closed (>= 1) */
+    uint32_t max_batch_eyes;     /* eyes per launch before a batch is closed (>= 1); every
+                                    request of a launch completes with its slowest item, and
+                                    the first request of a batch is always admitted, so a
+                                    limit near the typical request keeps large requests
+                                    alone (2^16 for requests of 2^8..2^18 eyes) */
     uint32_t max_batch_items;    /* requests per launch, 1..1024 */
     uint32_t eyes_per_wave;      /* 0 = tuned / default by hierarchy size; else 1, 2, 4 or 8 */
     float pairs_per_eye_guess;   /* output reservation per eye before any request on a

@@ -461,7 +461,7 @@ class Context:
 
     # -- serving ------------------------------------------------------------------
     def server_start(self, hbm_budget_bytes: int, max_inflight: int = 2,
-                     max_batch_eyes: int = 1 << 20, max_batch_items: int = 64,
+                     max_batch_eyes: int = 1 << 16, max_batch_items: int = 64,
                      eyes_per_wave: int = 0, pairs_per_eye_guess: float = 64.0,
                      overtake_ms: float = 100.0):
         cfg = HrrServerConfig(hbm_budget_bytes, max_inflight, max_batch_eyes, max_batch_items,
