@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import synth
-from _helpers import (pair_keys_from_gpu, pair_keys_from_oracle, per_eye_counts,
+from _helpers import (per_eye_fingerprints, pair_keys_from_gpu, pair_keys_from_oracle,
                       select_pairs_of_eyes)
 
 pytestmark = pytest.mark.gpu
@@ -508,8 +508,11 @@ def test_frame_scale_weights_sampled(ctx, orc):
 
 def test_frame_scale_sampled(ctx, orc):
     """1920x1080 eyes against 2^20 Gaussian-mixture lights in one launch (the
-    benchmark shape); sampled eyes compared pair for pair with the oracle, and
-    per-eye counts identical between the paper's sweep and the O(1) ablation."""
+    benchmark shape); sampled eyes compared pair for pair with the oracle,
+    every emitted pair checked against its own test, and every eye's
+    fingerprint (count and two 64-bit hash sums of its lights) identical
+    between the paper's method, the O(1) ablation and the aligned-block
+    closed form (a separate range-minimum implementation)."""
     import torch
     fr = synth.frame()
     h = ctx.build_hierarchy(fr["lights"], leaf_size=1)
@@ -524,15 +527,18 @@ def test_frame_scale_sampled(ctx, orc):
     out = orc.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], fr["lights"][perm],
                           fr["s"], lists=True)
     assert np.array_equal(select_pairs_of_eyes(pairs, sel), pair_keys_from_oracle(out, sel))
-    c0 = per_eye_counts(pairs, n_eyes)
-    assert int(c0.sum()) == n
-    assert np.array_equal(c0[sel], out["count"].astype(np.int64))
+    f0 = per_eye_fingerprints(pairs, n_eyes)
+    assert int(f0[0].sum()) == n
+    assert np.array_equal(f0[0][sel], out["count"].astype(np.int64))
     _assert_every_pair_passes_its_test(pairs, fr, perm)
     del pairs
     torch.cuda.empty_cache()
-    p2, n2, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n, rmq_method=1)
-    assert n2 == n
-    assert np.array_equal(per_eye_counts(p2, n_eyes), c0)
-    del p2
-    torch.cuda.empty_cache()
+    for method in (1, 4):
+        p2, n2, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n, rmq_method=method)
+        assert n2 == n
+        f2 = per_eye_fingerprints(p2, n_eyes)
+        for a, b in zip(f0, f2):
+            assert np.array_equal(a, b), method
+        del p2
+        torch.cuda.empty_cache()
     h.free()
