@@ -414,8 +414,10 @@ def _assert_every_pair_passes_its_test(pairs, fr, perm, chunk=1 << 27):
 
 def test_frame_scale_sampled_pow2_split(ctx, orc):
     """The frame against the power-of-two hierarchy of its 2^20 lights (every
-    node an aligned block): the same count as the radix hierarchy and sampled
-    eyes pair for pair against the oracle."""
+    node an aligned block): sampled eyes pair for pair against the oracle, and
+    every eye's pair fingerprint equal to the radix hierarchy's (the accepted
+    set does not depend on the hierarchy) and to the aligned-block closed
+    form's on the same hierarchy."""
     import torch
     fr = synth.frame()
     hr = ctx.build_hierarchy(fr["lights"], leaf_size=1)
@@ -432,8 +434,17 @@ def test_frame_scale_sampled_pow2_split(ctx, orc):
     out = orc.accept_eyes(fr["eyes"], sel, fr["width"], 0, fr["tile"], fr["lights"][perm],
                           fr["s"], lists=True)
     assert np.array_equal(select_pairs_of_eyes(pairs, sel), pair_keys_from_oracle(out, sel))
+    f0 = per_eye_fingerprints(pairs, n_eyes)
     del pairs
     torch.cuda.empty_cache()
+    for h, method in ((hr, 0), (hp, 4)):
+        p2, n2, _ = ctx.traverse(h, eyes, fr["s"], fr["width"], capacity=n, rmq_method=method)
+        assert n2 == n
+        f2 = per_eye_fingerprints(p2, n_eyes)
+        for a, b in zip(f0, f2):
+            assert np.array_equal(a, b), method
+        del p2
+        torch.cuda.empty_cache()
     hr.free()
     hp.free()
 
