@@ -102,15 +102,17 @@ HRR_HD uint32_t refine(uint32_t x, int keep, uint32_t a, uint32_t b) {
 // the seed is either the smallest member at or above a (then below b), or
 // one class step below it with bit `keep` set, so the first step lands on
 // that member.  Every step therefore ends at or above a, and only the bound
-// b is tested; the bits above j are 0u - (2u << j) (none for j = 31).
+// b is tested; the bits above j are 0u - (2u << j) (none for j = 31).  The
+// first step that would reach b ends the walk by emptying `todo`, so the
+// loop has a single exit (on the GPU: one lane mask to maintain per trip).
 HRR_HD uint32_t refine_inside(uint32_t x, int keep, uint32_t b) {
     uint32_t todo = x & ~low_mask(keep);   // keep = 32: nothing to walk
     while (todo) {
         const int j = bottom_bit(todo);
         const uint32_t step = 1u << j;
-        if (step >= b - x) break;
-        x += step;
-        todo = x & (0u - (2u << j));
+        const bool inside = step < b - x;
+        x = inside ? x + step : x;
+        todo = inside ? x & (0u - (2u << j)) : 0u;
     }
     return x;
 }
