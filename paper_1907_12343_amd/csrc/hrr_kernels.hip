@@ -825,11 +825,20 @@ void traverse_kernel(TravArgs A) {
                 // the child holding k inherits the minimum; the other one needs a query
                 const bool kLeft = k < c;
                 const uint32_t qa = kLeft ? c : a;
-                const uint32_t qb = act ? (kLeft ? b : c) : qa;
                 uint32_t kq = qa;
-                if (qb - qa > 1u) {
+                if (METHOD == 0 || METHOD == 5) {
+                    // the default method returns qa for a one-index range, so
+                    // it runs on every lane (inactive ones on [qa, qa + 1))
+                    // without a divergent guard
+                    const uint32_t qb = act ? (kLeft ? b : c) : qa + 1u;
                     kq = rmq<METHOD>(qa, qb, E.kr);
-                    if (STATS) ++st_rmq;
+                    if (STATS && qb - qa > 1u) ++st_rmq;
+                } else {
+                    const uint32_t qb = act ? (kLeft ? b : c) : qa;
+                    if (qb - qa > 1u) {
+                        kq = rmq<METHOD>(qa, qb, E.kr);
+                        if (STATS) ++st_rmq;
+                    }
                 }
                 kL = kLeft ? k : kq;
                 kR = kLeft ? kq : k;
@@ -892,7 +901,7 @@ void traverse_kernel(TravArgs A) {
             emit2<W>(O, D, emitL, make_uint2(E.u, a), wL, emitR, make_uint2(E.u, c), wR);
 
             // multi-light leaves
-            if (ballot(multi)) {
+            if (leaf > 1u && ballot(multi)) {   // one-light leaves are emitted above
                 uint64_t tests = 0;
                 leaf_lights<W>(O, D, E, a, mlN, c, mrN, tests);
                 if (STATS) st_leaf += tests;

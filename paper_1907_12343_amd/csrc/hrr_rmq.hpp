@@ -123,9 +123,8 @@ HRR_HD uint32_t refine_inside(uint32_t x, int keep, uint32_t b) {
 // bits met during the sweep; set an extra 1 at i + 1 when the prefix of k_r is
 // smaller than a's.
 HRR_HD uint32_t seed_candidate(uint32_t a, int i, uint32_t low) {
-    uint32_t x = (a & ~low_mask(i + 1)) | (1u << i) | low;
-    if (x < a && i < 31) x |= 1u << (i + 1);
-    return x;
+    const uint32_t x = (a & ~low_mask(i + 1)) | (1u << i) | low;
+    return x < a && i < 31 ? x | (2u << i) : x;
 }
 
 // The paper's range-minimum method (Section 2, Algorithms 2 and 3).
@@ -295,7 +294,8 @@ HRR_HD uint32_t rmq_paper_select(uint32_t a, uint32_t b, uint32_t kr) {
     // single candidate wins
     const int i = top_bit(z | 1u);
     const bool cls = !single && z != 0u;
-    const uint32_t x0 = cls ? seed_candidate(a, i, kr & low_mask(i)) : a;
+    const uint32_t seed = seed_candidate(a, i, kr & low_mask(i));   // evaluated on every lane (no branch)
+    const uint32_t x0 = cls ? seed : a;
     const int keep = single ? 32 : (cls ? i + 1 : 0);
     uint32_t k = refine_inside(x0, keep, b);
     k = at_g ? a + t_g : k;
