@@ -479,7 +479,7 @@ __device__ __forceinline__ void emit2(OutState& O, const ItemDesc& D, bool e0, u
     const uint32_t C = 1u << shift;
     const uint32_t pos0 = O.fill + count_below(m0);
     const uint32_t pos1 = O.fill + (uint32_t)__popcll(m0) + count_below(m1);
-    if (O.wp && O.fill + cnt <= C) {
+    if (O.wp && uni(O.fill) + cnt <= C) {
         if (e0) {
             put_pair(O.wp, pos0, p0);
             if (W) put_weight(O.ww, pos0, w0);
@@ -725,8 +725,14 @@ void traverse_kernel(TravArgs A) {
         }
 
         // -------- top-down walk --------
-        while (S.n + S.g > 0) {
-            if (S.n < kWave && S.g > 0) stack_refill(S, L, spill, cap);
+        // the node records' base, wave-uniform in scalar registers for the
+        // whole walk (the loads take it as their scalar base)
+        const Node* const nodes = reinterpret_cast<const Node*>(uni64((unsigned long long)(size_t)D.nodes));
+        // the loop and refill conditions are written as one scalar compare
+        // each (S.n < 64 && S.g > 0 is (S.n >> 6) < min(S.g, 1)); as && / +
+        // the compiler builds them from two compares merged in lane masks
+        while ((S.n | S.g) != 0u) {
+            if ((S.n >> 6) < min(S.g, 1u)) stack_refill(S, L, spill, cap);
             // the wave issues its record loads at raised priority, so that
             // they leave early (frame 142.9 -> 142.1 ms)
             __builtin_amdgcn_s_setprio(1);
@@ -780,7 +786,7 @@ void traverse_kernel(TravArgs A) {
                 typedef __attribute__((address_space(1))) const unsigned char* gbytes;
                 typedef __attribute__((address_space(1))) const void* gptr;
                 typedef __attribute__((address_space(3))) void* lptr;
-                const gbytes rec = (gbytes)(D.nodes);
+                const gbytes rec = (gbytes)(nodes);
                 __builtin_amdgcn_global_load_lds((gptr)(rec + o0), (lptr)(size_t)(xlds), 16, 0, 0);
                 __builtin_amdgcn_global_load_lds((gptr)(rec + o1), (lptr)(size_t)(xlds + kSlab), 16, 0, 0);
                 __builtin_amdgcn_global_load_lds((gptr)(rec + o2), (lptr)(size_t)(xlds + 2 * kSlab), 16, 0, 0);
