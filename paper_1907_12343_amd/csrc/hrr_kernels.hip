@@ -729,10 +729,11 @@ void traverse_kernel(TravArgs A) {
         // whole walk (the loads take it as their scalar base)
         const Node* const nodes = reinterpret_cast<const Node*>(uni64((unsigned long long)(size_t)D.nodes));
         // the loop and refill conditions are written as one scalar compare
-        // each (S.n < 64 && S.g > 0 is (S.n >> 6) < min(S.g, 1)); as && / +
-        // the compiler builds them from two compares merged in lane masks
+        // each (S.g is a multiple of 64, so S.n < 64 && S.g > 0 is
+        // S.n < min(S.g, 64)); as && / + the compiler builds them from two
+        // compares merged in lane masks
         while ((S.n | S.g) != 0u) {
-            if ((S.n >> 6) < min(S.g, 1u)) stack_refill(S, L, spill, cap);
+            if (S.n < min(S.g, (uint32_t)kStackUnit)) stack_refill(S, L, spill, cap);
             // the wave issues its record loads at raised priority, so that
             // they leave early (frame 142.9 -> 142.1 ms)
             __builtin_amdgcn_s_setprio(1);
