@@ -230,7 +230,10 @@ typedef struct hrr_traverse_opts {
 typedef struct hrr_stats {
     uint64_t eyes;          /* (virtual) eyes traversed */
     uint64_t pairs;         /* accepted pairs (true count, also past capacity) */
-    uint64_t node_visits;   /* internal nodes popped (each tests both children) */
+    uint64_t node_visits;   /* internal nodes popped (each tests both children); a
+                               one-eye-per-wave walk, which starts by testing the
+                               hierarchy's top (the nodes of depth 6 and the leaves
+                               above), adds half a visit per tested entry */
     uint64_t rmq_calls;     /* range minima computed with the paper's method */
     uint64_t leaf_tests;    /* exact tests of lights inside leaves of several lights (or of a
                                hierarchy that is a single leaf); a one-light child is decided by

@@ -16,6 +16,8 @@
 #include "hrr_layout.hpp"
 
 extern "C" hipError_t hrr_noalloc_scratch(int device, void** out);   // hrr_kernels.hip
+extern "C" hipError_t hrr_launch_frontier(const hrr::Node* nodes, uint32_t n_lights, uint32_t leaf_size, float* out,
+                                          hipStream_t stream);   // hrr_kernels.hip
 
 #define HRR_EXPORT extern "C" __attribute__((visibility("default")))
 
@@ -286,6 +288,20 @@ HRR_EXPORT hrr_status hrr_range_min(hrr_ctx* ctx, const uint32_t* a, const uint3
 // hierarchy
 // ---------------------------------------------------------------------------
 
+namespace hrr {
+
+hrr_status attach_frontier(hrr_hierarchy* h, hipStream_t stream) {
+    if (!h->n_nodes) return HRR_OK;
+    const size_t fb = ((size_t)kFrontierMax * kFrontierFloats + 1) * sizeof(float);
+    hipError_t e = hipMalloc((void**)&h->d_frontier, fb);
+    if (e == hipSuccess) e = hrr_launch_frontier(h->d_nodes, h->n_lights, h->leaf_size, h->d_frontier, stream);
+    if (e != hipSuccess) return hip_fail(e, "hierarchy top");
+    h->device_bytes += fb;
+    return HRR_OK;
+}
+
+}  // namespace hrr
+
 HRR_EXPORT hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz, uint32_t n_lights, uint32_t leaf_arg,
                                           const float* box, hrr_hierarchy** out) {
     if (!ctx || !out) return fail(HRR_E_INVALID, "hrr_build_hierarchy: null argument");
@@ -331,6 +347,15 @@ HRR_EXPORT hrr_status hrr_build_hierarchy(hrr_ctx* ctx, const float* lights_xyz,
         return hip_fail(e, "hierarchy upload");
     }
     h->device_bytes = nb + lb + pb;
+    hrr_status st = attach_frontier(h, nullptr);
+    if (st == HRR_OK && h->d_frontier &&
+        (e = hipMemcpy(&h->n_frontier, h->d_frontier + (size_t)kFrontierMax * kFrontierFloats, sizeof(uint32_t),
+                       hipMemcpyDeviceToHost)) != hipSuccess)
+        st = hip_fail(e, "hierarchy top");
+    if (st != HRR_OK) {
+        hrr_free_hierarchy(ctx, h);
+        return st;
+    }
     h->perm = std::move(H.perm);
     h->sorted_xyz = std::move(H.sorted_xyz);
     *out = h;
@@ -396,6 +421,7 @@ HRR_EXPORT void hrr_free_hierarchy(hrr_ctx* ctx, hrr_hierarchy* h) {
     if (!h) return;
     if (ctx) (void)hipSetDevice(ctx->device);
     if (h->d_nodes) (void)hipFree(h->d_nodes);
+    if (h->d_frontier) (void)hipFree(h->d_frontier);
     if (h->d_lights) (void)hipFree(h->d_lights);
     if (h->d_perm) (void)hipFree(h->d_perm);
     delete h;

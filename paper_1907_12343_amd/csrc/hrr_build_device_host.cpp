@@ -189,6 +189,11 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
             return fail_free(hip_fail(e, "root box"));
         h->n_nodes = n_records;
         h->depth = (uint32_t)(levels - 1);
+        const hrr_status st = attach_frontier(h, stream);
+        if (st != HRR_OK) return fail_free(st);
+        if ((e = hipMemcpyAsync(pin + 4, h->d_frontier + (size_t)kFrontierMax * kFrontierFloats, sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, stream)) != hipSuccess)
+            return fail_free(hip_fail(e, "hierarchy top"));
     } else if (n) {
         if ((e = hrr_dev_root_leaf_box(reinterpret_cast<const float4*>(h->d_lights), n, d_box, stream)) != hipSuccess)
             return fail_free(hip_fail(e, "root box"));
@@ -200,6 +205,7 @@ HRR_EXPORT hrr_status hrr_build_hierarchy_device(hrr_ctx* ctx, const float* ligh
         (e = hipStreamSynchronize(stream)) != hipSuccess)
         return fail_free(hip_fail(e, "device build"));
     if (pin[2]) return fail_free(fail(HRR_E_INVALID, "non-finite light coordinate"));
+    if (h->d_frontier) h->n_frontier = pin[4];
     memcpy(h->box, root_box, sizeof root_box);
     *out = h;
     return HRR_OK;

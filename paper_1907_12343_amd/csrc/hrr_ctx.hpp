@@ -19,6 +19,8 @@ struct hrr_hierarchy {
     uint32_t split = HRR_SPLIT_RADIX;
     float box[6] = {0, 0, 0, 0, 0, 0};
     hrr::Node* d_nodes = nullptr;
+    float* d_frontier = nullptr;      // kFrontierMax entries of kFrontierFloats, then the entry count
+    uint32_t n_frontier = 0;
     float* d_lights = nullptr;       // float4 per light
     uint32_t* d_perm = nullptr;
     // host copies (filled on demand for hierarchies built on the device)
@@ -158,6 +160,10 @@ double timed_kernel_ms(LaunchScratch& S);
 hrr_status finish_items(hrr_ctx* ctx, LaunchScratch& S);
 
 void release_scratch(LaunchScratch& S);
+
+// Allocate h->d_frontier and enqueue the computation of the hierarchy's top
+// (the entry count lands in the table's last word) on `stream`.
+hrr_status attach_frontier(hrr_hierarchy* h, hipStream_t stream);
 
 // The allocation-free traversal of one eye set (hrr_traverse_noalloc): every
 // launch on `stream`, nothing allocated, nothing read back.

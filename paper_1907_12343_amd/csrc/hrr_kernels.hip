@@ -706,6 +706,51 @@ void traverse_kernel(TravArgs A) {
                 if (STATS) st_leaf += tests;
                 continue;
             }
+            if (EPW == 1 && D.n_frontier > 0) {
+                // one eye per wave: lane t tests entry t of the hierarchy's top
+                // (its range minimum, its box; a leaf entry is tested as a leaf
+                // child is), surviving nodes are pushed in index order
+                const bool fa = lane < D.n_frontier;
+                uint32_t a = 0, b = 1, rec = 0xFFFFFFFFu;
+                float4 f0 = make_float4(0.f, 0.f, 0.f, 0.f), f1 = f0;
+                if (fa) {
+                    const float4* f = reinterpret_cast<const float4*>(D.frontier) + 3u * lane;
+                    f0 = f[0];
+                    f1 = f[1];
+                    a = __float_as_uint(f0.w);
+                    b = __float_as_uint(f1.w);
+                    rec = __float_as_uint(f[2].x);
+                }
+                const uint32_t n = b - a;
+                uint32_t k = a;
+                if (METHOD == 0 || METHOD == 5) {
+                    k = rmq<METHOD>(a, b, E.kr);   // a one-index range gives a
+                } else if (n > 1u) {
+                    k = rmq<METHOD>(a, b, E.kr);
+                }
+                if (STATS && fa && n > 1u) ++st_rmq;
+                const uint32_t v = rotated(k, E.R);
+                const float d2 = box_d2(E.ex, E.ey, E.ez, f0.x, f0.y, f0.z, f1.x, f1.y, f1.z);
+                bool kept = false;
+                if (fa) kept = rr_test(v, D, d2, n == 1u);
+                const bool push = kept && rec != 0xFFFFFFFFu;
+                const bool emit = kept && rec == 0xFFFFFFFFu && n == 1u;
+                const bool multi = kept && rec == 0xFFFFFFFFu && n > 1u;
+                float w = 0.0f;
+                if (W && emit) w = 1.0f / accept_p(s, d2, 1.0f);
+                const uint64_t m = ballot(push);
+                if (push) L.stack[count_below(m)] = make_uint2(rec, k);
+                S.n = (uint32_t)__popcll(m);
+                wave_sync();
+                // each pair of entries is one parent's two child tests
+                if (STATS) st_visits += (D.n_frontier + 1u) / 2u;
+                emit2<W>(O, D, emit, make_uint2(E.u, a), w, false, make_uint2(0u, 0u), 0.0f);
+                if (ballot(multi)) {
+                    uint64_t tests = 0;
+                    leaf_lights<W>(O, D, E, a, multi ? n : 0u, 0u, 0u, tests);
+                    if (STATS) st_leaf += tests;
+                }
+            } else {
             bool push = false;
             uint32_t k0 = 0;
             if (act) {
@@ -722,6 +767,7 @@ void traverse_kernel(TravArgs A) {
             }
             S.n = (uint32_t)__popcll(m);
             wave_sync();
+            }
         }
 
         // -------- top-down walk --------
@@ -940,6 +986,65 @@ void traverse_kernel(TravArgs A) {
             atomicMax(A.stats + ST_MAXSTACK, (unsigned long long)mx);
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// the top of a hierarchy (the one-eye-per-wave walk's starting entries)
+// ---------------------------------------------------------------------------
+//
+// One wave expands the root kFrontierDepth times: every internal entry is
+// replaced by its two children (their boxes and ranges come from its record,
+// their records are `first` and `first + 1` when internal), leaves stay.
+// Entries keep index order; after level l there are at most 2^l of them.
+// The root's own box is never needed: the root is internal (the caller only
+// runs this for hierarchies with records) and is always expanded.
+__global__ __launch_bounds__(64) void frontier_kernel(const Node* __restrict__ nodes, uint32_t n_lights,
+                                                      uint32_t leaf, float* __restrict__ out) {
+    struct Entry { uint32_t a, b, rec; float lo[3], hi[3]; };
+    __shared__ Entry next[kFrontierMax];
+    const uint32_t t = threadIdx.x;
+    Entry e;
+    e.a = 0u; e.b = n_lights; e.rec = 0u;
+    for (int q = 0; q < 3; ++q) { e.lo[q] = 0.0f; e.hi[q] = 0.0f; }
+    uint32_t n = 1;
+    for (uint32_t level = 0; level < kFrontierDepth; ++level) {
+        const bool have = t < n;
+        const bool internal = have && e.rec != 0xFFFFFFFFu;
+        const uint32_t c = have ? (internal ? 2u : 1u) : 0u;
+        // exclusive prefix of c over the wave
+        uint32_t inc = c;
+        for (uint32_t off = 1; off < 64u; off <<= 1) {
+            const uint32_t y = __shfl_up(inc, off, 64);
+            if (t >= off) inc += y;
+        }
+        const uint32_t pos = inc - c;
+        const uint32_t total = __shfl(inc, 63, 64);
+        if (internal) {
+            const Node R = nodes[e.rec];
+            Entry L, Rt;
+            L.a = R.a; L.b = R.c; L.rec = R.c - R.a > leaf ? R.first : 0xFFFFFFFFu;
+            Rt.a = R.c; Rt.b = R.b; Rt.rec = R.b - R.c > leaf ? R.first + 1u : 0xFFFFFFFFu;
+            for (int q = 0; q < 3; ++q) {
+                L.lo[q] = R.lo_l[q]; L.hi[q] = R.hi_l[q];
+                Rt.lo[q] = R.lo_r[q]; Rt.hi[q] = R.hi_r[q];
+            }
+            next[pos] = L;
+            next[pos + 1u] = Rt;
+        } else if (have) {
+            next[pos] = e;
+        }
+        __syncthreads();
+        n = total;
+        if (t < n) e = next[t];
+        __syncthreads();
+    }
+    if (t < n) {
+        float* o = out + (size_t)t * kFrontierFloats;
+        o[0] = e.lo[0]; o[1] = e.lo[1]; o[2] = e.lo[2]; o[3] = __uint_as_float(e.a);
+        o[4] = e.hi[0]; o[5] = e.hi[1]; o[6] = e.hi[2]; o[7] = __uint_as_float(e.b);
+        o[8] = __uint_as_float(e.rec); o[9] = 0.0f; o[10] = 0.0f; o[11] = 0.0f;
+    }
+    if (t == 0) reinterpret_cast<uint32_t*>(out)[kFrontierMax * kFrontierFloats] = n;
 }
 
 // ---------------------------------------------------------------------------
@@ -1337,6 +1442,14 @@ extern "C" hipError_t hrr_traverse_occupancy(uint32_t eyes_per_wave, uint32_t me
     }
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, hrr::kWave * hrr::kWavesPerBlock,
                                                         lds_per_block);
+}
+
+// The top of a hierarchy with records (see frontier_kernel): out holds
+// kFrontierMax * kFrontierFloats floats, then the entry count.
+extern "C" hipError_t hrr_launch_frontier(const hrr::Node* nodes, uint32_t n_lights, uint32_t leaf_size, float* out,
+                                          hipStream_t stream) {
+    hipLaunchKernelGGL(hrr::frontier_kernel, dim3(1), dim3(64), 0, stream, nodes, n_lights, leaf_size, out);
+    return hipGetLastError();
 }
 
 // Processing order of the virtual eyes of a launch (see order_keys_kernel).

@@ -234,6 +234,8 @@ hrr_status launch_items(hrr_ctx* ctx, LaunchScratch& S, const std::vector<HostIt
         const ItemMeta& m = M[k];
         ItemDesc& D = S.h_items[pos];
         D.nodes = h->d_nodes;
+        D.frontier = h->d_frontier;
+        D.n_frontier = h->n_frontier;
         D.lights = h->d_lights;
         D.eyes = it.eyes.xyz;
         D.pairs = pairs ? pairs + 2 * it.out_offset : nullptr;
@@ -450,6 +452,8 @@ hrr_status launch_noalloc(hrr_ctx* ctx, const hrr_hierarchy* h, const hrr_eyes& 
     ItemDesc D;
     memset(&D, 0, sizeof D);
     D.nodes = h->d_nodes;
+    D.frontier = h->d_frontier;
+    D.n_frontier = h->n_frontier;
     D.lights = h->d_lights;
     D.eyes = eyes.xyz;
     D.pairs = pairs;

@@ -39,6 +39,7 @@ static_assert(sizeof(Node) == 64, "node record must be 64 bytes");
 // virtual eye u is eye u / N, sample u % N.
 struct ItemDesc {
     const Node* nodes;
+    const float* frontier;        // the hierarchy's top (kFrontierFloats per entry), n_frontier entries
     const float* lights;          // 4 floats per light (x, y, z, 0), sequence order
     const float* eyes;            // 3 floats per eye
     uint32_t* pairs;              // item's output slice, 2 u32 per pair
@@ -55,12 +56,25 @@ struct ItemDesc {
     uint32_t n_lights, n_nodes, leaf_size, n_virtual;
     uint32_t width, shift_offset, pixel_base, n_samples;
     uint32_t psi_s0, task_begin;
+    uint32_t n_frontier, pad_frontier;
     float s;
     // product-form keep test (set by the host): v is culled when
     // float(v) * d2 > t_cull, kept (one light) when < t_keep, for d2 <= d2_fast
     float t_cull, t_keep, d2_fast;
     float root_lo[3], root_hi[3];
 };
+
+// The top of a hierarchy, where a one-eye-per-wave walk starts: the nodes of
+// depth kFrontierDepth and the leaves above that depth, in index order, at
+// most 2^kFrontierDepth = 64 entries (one per lane).  Every root-to-leaf path
+// crosses exactly one entry, so testing the entries in place of the nodes
+// above them culls no more (each test is conservative on its own) and skips
+// the walk's first, nearly empty steps.  Entry layout, three float4:
+// (lo.x, lo.y, lo.z, a), (hi.x, hi.y, hi.z, b), (record, 0, 0, 0), with a, b
+// (the range [a, b)) and the node's record (0xFFFFFFFF for a leaf) as bits.
+constexpr uint32_t kFrontierDepth = 6;
+constexpr uint32_t kFrontierMax = 1u << kFrontierDepth;
+constexpr uint32_t kFrontierFloats = 12;
 
 // Eye-ordering description of one item: eyes are bucketed by the Morton
 // cell of their position inside the item's light box (cell = (x - lo) * scale,

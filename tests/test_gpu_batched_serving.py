@@ -95,8 +95,10 @@ def test_batched_items_equal_plain_and_oracle(ctx, orc):
 def test_batched_groups_by_hierarchy_size(ctx, hrr):
     """Items whose hierarchies want different eyes per wave (8 below 2^16
     lights, 4 below 2^17, else 1) run as one launch per group; every item
-    equals a plain one-eye-per-wave launch pair for pair and weight for
-    weight, work statistics add up exactly, and an overflow stays per item."""
+    equals a plain launch of its group's shape pair for pair and weight for
+    weight, work statistics add up exactly (one-eye-per-wave walks start at
+    the hierarchy's top, several eyes per wave at the root, so the shapes
+    must agree for the counts to), and an overflow stays per item."""
     import torch
     sizes = [1 << 11, (1 << 17) + 5, 1 << 16, 1 << 12, 1 << 18, 1 << 11]
     caches = []
@@ -109,8 +111,10 @@ def test_batched_groups_by_hierarchy_size(ctx, hrr):
                            width=d["width"], s=d["s"]))
     hs = [ctx.build_hierarchy(d["lights"]) for d in caches]
     eyes = [_dev(ctx, d["eyes"]) for d in caches]
-    plain = [ctx.traverse_all(h, e, d["s"], d["width"], eyes_per_wave=1, stack_entries=512,
-                              with_weights=True, stats=True)
+    def group_epw(n):
+        return 1 if n >= 1 << 17 else (4 if n >= 1 << 16 else 8)
+    plain = [ctx.traverse_all(h, e, d["s"], d["width"], eyes_per_wave=group_epw(d["lights"].shape[0]),
+                              stack_entries=512, with_weights=True, stats=True)
              for h, e, d in zip(hs, eyes, caches)]
     counts = [p[1] for p in plain]
     offs = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
