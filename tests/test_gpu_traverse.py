@@ -268,6 +268,28 @@ def test_small_and_root_leaf_hierarchies(ctx, orc, n_l, leaf):
     h.free()
 
 
+@pytest.mark.parametrize("split", ["radix", "pow2"])
+@pytest.mark.parametrize("n_l,leaf", [(33, 1), (64, 1), (65, 1), (100, 3), (127, 1), (128, 3), (129, 1),
+                                      (200, 3), (300, 8)])
+def test_walk_start_at_the_hierarchy_top(ctx, orc, n_l, leaf, split):
+    """One-eye-per-wave walks start from the hierarchy's top (the nodes of
+    depth 6 and the leaves above it).  Light counts around 2^6 with leaf sizes
+    1, 3 and 8 make tops that mix leaves of every depth with internal nodes,
+    in both split rules; the accepted set equals the oracle's all-pairs set
+    and the several-eyes-per-wave walk, which starts at the root."""
+    lights = synth.mixture_points(n_l, np.random.default_rng(700 + n_l).random((4, 3)), 710 + n_l)
+    eyes = synth.uniform_points(500, 720 + n_l)
+    tile = synth.dither_tile(100)
+    h = ctx.build_hierarchy(lights, leaf_size=leaf, split=split)
+    sel = np.arange(500)
+    out = orc.accept_eyes(eyes, sel, 64, 0, tile, h.sorted_lights(), 0.02, lists=True)
+    want = pair_keys_from_oracle(out, sel)
+    for epw in (1, 8):
+        pairs, n, _ = ctx.traverse_all(h, _eyes_t(ctx, eyes), 0.02, 64, eyes_per_wave=epw)
+        assert np.array_equal(pair_keys_from_gpu(pairs), want), epw
+    h.free()
+
+
 def test_keep_decisions_at_the_threshold(ctx, orc):
     """s chosen so that p 2^32 lands within a few units of a pair's xi: the
     fast reciprocal band must hand every such case to the exact division."""
